@@ -1,0 +1,150 @@
+"""Pins of the team reward (Section IV-A), success and objective (Section III):
+brute-force loops on small teams, closed forms and permutation invariance."""
+import math
+
+import numpy as np
+
+from oracle import fitness
+from paper_2503_12204_amd import workloads as W
+
+
+def _brute(prob, x, goal, fp32=False):
+    """Explicit per-sample, per-step, per-pair loops (small teams only)."""
+    dx, du, dp = W.dims(prob.dyn)
+    M, n, T1, _ = x.shape
+    T = T1 - 1
+    thr = 2 * float(np.float32(prob.robot_radius)) + float(np.float32(prob.safety_margin))
+    thr2 = thr * thr
+    rs, hs, rh = [], [], []
+    for m in range(M):
+        tot, hits, robots_hit = 0.0, 0, 0
+        for k in range(n):
+            d0 = max(math.dist(x[m, k, 0, :dp], goal[k]), float(np.float32(prob.d0_floor)))
+            for t in range(1, T + 1):
+                tot += 1.0 - math.dist(x[m, k, t, :dp], goal[k]) / d0
+                partners = 0
+                for l in range(n):
+                    if l == k:
+                        continue
+                    if fp32:
+                        acc = np.float32(0)
+                        for c in range(dp):
+                            dc = np.float32(x[m, k, t, c]) - np.float32(x[m, l, t, c])
+                            acc = np.float32(dc * dc) if c == 0 else np.float32(acc + np.float32(dc * dc))
+                        hit = acc <= np.float32(thr2)
+                    else:
+                        hit = sum((x[m, k, t, c] - x[m, l, t, c]) ** 2 for c in range(dp)) <= thr2
+                    if hit:
+                        partners += 1
+                        if k < l:
+                            hits += 1
+                if partners:
+                    robots_hit += 1
+                    tot -= float(np.float32(prob.w_safe)) * (partners if prob.flags & W.FLAG_SAFE_PAIRS else 1)
+        rs.append(tot / (n * T))
+        hs.append(hits)
+        rh.append(robots_hit)
+    return np.array(rs), np.array(hs), np.array(rh)
+
+
+def _random_traj(rng, M, n, T, dx, scale=1.0):
+    return rng.normal(size=(M, n, T + 1, dx)) * scale
+
+
+def test_matches_brute_force_small_teams():
+    rng = np.random.default_rng(0)
+    for dyn in (W.HOLO2D, W.HOLO3D, W.UNICYCLE):
+        for n in (2, 3):
+            for flags in (0, W.FLAG_SAFE_PAIRS):
+                p = W.Problem(dyn=dyn, n_robots=n, horizon=6, flags=flags, w_safe=0.7)
+                dx, _, dp = W.dims(dyn)
+                x = _random_traj(rng, 5, n, 6, dx, scale=0.6)
+                g = rng.normal(size=(n, dp))
+                r, h, rh = fitness.reward(p, x, g)
+                br, bh, brh = _brute(p, x, g)
+                assert np.allclose(r, br, atol=1e-13)
+                assert np.array_equal(h, bh) and np.array_equal(rh, brh)
+                assert h.sum() > 0  # the case exercises collisions
+                x32 = x.astype(np.float32)
+                r, h, rh = fitness.reward(p, x32, g, pred_dtype=np.float32)
+                br, bh, brh = _brute(p, x32.astype(np.float64), g, fp32=True)
+                assert np.array_equal(h, bh) and np.array_equal(rh, brh)
+
+
+def test_head_on_pass_closed_form():
+    # two robots on a line approach each other at speed v each
+    T, dt, v, d0 = 40, 0.1, 0.55, 3.0
+    p = W.Problem(dyn=W.HOLO2D, n_robots=2, horizon=T)
+    t = np.arange(T + 1) * dt
+    x = np.zeros((1, 2, T + 1, 4))
+    x[0, 0, :, 0] = -d0 / 2 + v * t
+    x[0, 1, :, 0] = d0 / 2 - v * t
+    _, h, rh = fitness.reward(p, x, np.array([[d0 / 2, 0], [-d0 / 2, 0]]))
+    sep = np.abs(d0 - 2 * v * t[1:])
+    expect = int((sep <= 0.7 - 1e-12).sum())   # 2 R_a + epsilon = 0.7, no step lands on it
+    assert np.all(np.abs(sep - 0.7) > 1e-9)
+    assert h[0] == expect and rh[0] == 2 * expect
+
+
+def test_goal_term_endpoints_and_stationary_team():
+    p = W.Problem(dyn=W.HOLO2D, n_robots=3, horizon=10)
+    start = np.array([[0.0, 0.0], [5.0, 0.0], [0.0, 5.0]])
+    goal = np.array([[3.0, 4.0], [5.0, 2.0], [-1.0, 5.0]])
+    x = np.zeros((2, 3, 11, 4))
+    x[0, :, :, :2] = start[:, None, :]          # stays at the start: r_goal = 0
+    x[1, :, 0, :2] = start
+    x[1, :, 1:, :2] = goal[:, None, :]          # at the goal from t = 1: r_goal = 1
+    r, h, _ = fitness.reward(p, x, goal)
+    assert abs(r[0]) < 1e-15 and abs(r[1] - 1.0) < 1e-15 and h.sum() == 0
+    # stationary team half way: r_goal = 1/2 for every robot-step
+    x[1, :, 1:, :2] = (0.5 * (start + goal))[:, None, :]
+    r, _, _ = fitness.reward(p, x, goal)
+    assert abs(r[1] - 0.5) < 1e-15
+    # start on the goal: the floored denominator applies
+    x2 = np.zeros((1, 3, 11, 4))
+    x2[0, :, :, :2] = goal[:, None, :]
+    x2[0, 0, 1:, 0] += 0.05
+    r, _, _ = fitness.reward(p, x2, goal)
+    assert abs(r[0] - (1.0 - (0.05 / 0.1) / 3)) < 1e-7
+
+
+def test_permutation_invariance():
+    rng = np.random.default_rng(3)
+    p = W.Problem(dyn=W.HOLO3D, n_robots=7, horizon=9)
+    x = _random_traj(rng, 4, 7, 9, 6, scale=0.8)
+    g = rng.normal(size=(7, 3))
+    perm = rng.permutation(7)
+    a = fitness.reward(p, x, g)
+    b = fitness.reward(p, x[:, perm], g[perm])
+    assert np.allclose(a[0], b[0], atol=1e-14)
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_fp32_predicate_at_threshold():
+    p = W.Problem(dyn=W.HOLO2D, n_robots=2, horizon=1)
+    thr2 = fitness.threshold_sq(p, np.float32)
+    # pair whose FP32 squared distance is exactly thr2 (dy = 0, dx = sqrt(thr2) if representable)
+    dxs = np.float32(np.sqrt(np.float64(thr2)))
+    assert np.float32(dxs * dxs) <= thr2 or np.float32(np.nextafter(dxs, 0) ** 2) <= thr2
+    x = np.zeros((2, 2, 2, 4), dtype=np.float32)
+    x[0, 1, 1, 0] = dxs
+    x[1, 1, 1, 0] = np.nextafter(dxs, np.float32(10))
+    x[1, 1, 1, 0] = np.nextafter(x[1, 1, 1, 0], np.float32(10))
+    _, h, _ = fitness.reward(p, x, np.zeros((2, 2)), pred_dtype=np.float32)
+    assert h[0] == int(np.float32(dxs * dxs) <= thr2) and h[1] == 0
+
+
+def test_success_and_objective():
+    p = W.Problem(dyn=W.HOLO2D, n_robots=2, horizon=4, goal_tol=0.1)
+    goal = np.array([[1.0, 0.0], [-1.0, 0.0]])
+    x = np.zeros((3, 2, 5, 4))
+    x[:, 0, :, 0] = np.linspace(-1, 1, 5)
+    x[:, 1, :, 0] = np.linspace(1, -1, 5)
+    x[:, 1, :, 1] = 0.61            # always 0.61 apart in y: safe (> 0.6)
+    x[1, 1, :, 1] = 0.6             # exactly 2 R_a: unsafe (strict)
+    x[2, 1, -1, 0] = -0.8           # terminal miss
+    x[:, 1, -1, 1] = 0.0
+    s = fitness.success(p, x, goal)
+    assert list(s) == [True, False, False]
+    o = fitness.objective(p, x, goal)
+    assert abs(o[0] - 2 / 8) < 1e-15 and abs(o[2] - 1 / 8) < 1e-15

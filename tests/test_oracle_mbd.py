@@ -1,0 +1,124 @@
+"""Pins of the Monte Carlo score update (Eqs. denoising, guidance, mc,
+mbd-denoising; Algorithms 1 and 2)."""
+import numpy as np
+
+from oracle import dynamics, mbd, noise, schedule
+from paper_2503_12204_amd import workloads as W
+
+
+def test_weights_sum_to_one_and_degenerate_cases():
+    rng = np.random.default_rng(0)
+    r = rng.normal(size=1000)
+    for norm in (True, False):
+        w = mbd.weights(r, 0.1, norm)
+        assert abs(w.sum() - 1) < 1e-12 and (w >= 0).all()
+    w = mbd.weights(np.full(37, 0.3), 0.1, True)
+    assert np.allclose(w, 1 / 37, atol=1e-15)
+    w = mbd.weights(r, 1e12, True)
+    assert np.allclose(w, 1 / 1000, rtol=1e-9)
+    # argmax limit as the temperature vanishes (distinct rewards)
+    w = mbd.weights(r, 1e-6, False)
+    assert w[np.argmax(r)] > 1 - 1e-12
+
+
+def test_normalised_weights_equal_plain_weights_at_scaled_temperature():
+    rng = np.random.default_rng(1)
+    r = rng.normal(size=500) * 0.03 + 0.4
+    sd = np.sqrt(((r - r.mean()) ** 2).mean())
+    assert np.allclose(mbd.weights(r, 0.1, True), mbd.weights(r, 0.1 * sd, False), rtol=1e-10)
+
+
+def _is_stats(samples, w):
+    ubar = (w[:, None] * samples).sum(0)
+    se = np.sqrt((w[:, None] ** 2 * (samples - ubar) ** 2).sum(0))
+    return ubar, se
+
+
+def test_linear_fitness_exponential_tilt():
+    """r = g.u: the weighted mean of N(mu, s2 I) samples tends to mu + s2 g / lambda."""
+    rng = np.random.default_rng(2)
+    D, M, lam = 4, 400_000, 0.5
+    mu = rng.normal(size=D)
+    g = rng.normal(size=D) * 0.3
+    ms_i, sg_i = 1.3, 0.7
+    du_i = mu / ms_i
+    eps = rng.normal(size=(D, M))
+    samples = mbd.sample_deformations(du_i, eps, ms_i, sg_i)
+    r = samples @ g
+    du_next, w = mbd.mc_update(du_i, eps, r, ms_i, sg_i, 1.0, lam, normalize=False)
+    expect = mu + sg_i ** 2 * g / lam
+    _, se = _is_stats(samples, w)
+    assert np.all(np.abs(du_next - expect) <= 4 * se + 1e-12)
+
+
+def test_quadratic_fitness_posterior_and_smoothed_score():
+    """r = -|u - u*|^2 / (2 s): the MC mean tends to the Gaussian posterior mean,
+    and Eq. guidance with that mean is the exact score of the noised density."""
+    rng = np.random.default_rng(3)
+    D, M, lam, s = 5, 400_000, 0.5, 4.0
+    sched = schedule.step_scalars(100, 1e-4, 1e-2)
+    ab = schedule.alpha_bar(100, 1e-4, 1e-2)
+    i = 60
+    ms, sg, os_ = sched[0][i], sched[1][i], sched[2][i]
+    tau_i = rng.normal(size=D)
+    ustar = rng.normal(size=D)
+    eps = rng.normal(size=(D, M))
+    samples = mbd.sample_deformations(tau_i, eps, ms, sg)
+    r = -((samples - ustar) ** 2).sum(1) / (2 * s)
+    tau_prev, w = mbd.mc_update(tau_i, eps, r, ms, sg, os_, lam, normalize=False)
+    mu, s2 = tau_i * ms, sg ** 2
+    post = (s * lam * mu + s2 * ustar) / (s * lam + s2)
+    _, se = _is_stats(samples, w)
+    assert np.all(np.abs(tau_prev / os_ - post) <= 4 * se)
+    # Eq. guidance with the posterior mean equals the score of p_i = p_0 * forward noise
+    a = ab[i]
+    guided = -tau_i / (1 - a) + np.sqrt(a) / (1 - a) * post
+    exact = (np.sqrt(a) * ustar - tau_i) / (a * s * lam + 1 - a)
+    assert np.allclose(guided, exact, rtol=1e-12, atol=1e-12)
+    # Eq. denoising with that score equals Eq. mbd-denoising
+    alpha_i = a / ab[i - 1]
+    denoised = (tau_i + (1 - a) * guided) / np.sqrt(alpha_i)
+    assert np.allclose(denoised, np.sqrt(ab[i - 1]) * post, rtol=1e-12)
+
+
+def test_zero_spread_is_pure_rescale():
+    du_i = np.array([0.3, -1.2, 2.0])
+    out, _ = mbd.mc_update(du_i, np.ones((3, 8)), np.arange(8.0), 1.7, 0.0, 0.9, 0.1)
+    assert np.allclose(out, 0.9 * 1.7 * du_i, rtol=1e-15)
+
+
+def test_dimension_count_and_rollout_count(monkeypatch):
+    # 16 2D-holonomic robots at H = 100 have 3200 optimisation variables
+    assert W.Problem(dyn=W.HOLO2D, n_robots=16, horizon=100).D == 3200
+    # K iterations of N steps roll out K*N*M sample trajectories plus K final ones
+    calls = []
+    orig = dynamics.rollout
+
+    def counting(prob, x0, u):
+        calls.append(np.asarray(u).shape[0])
+        return orig(prob, x0, u)
+
+    monkeypatch.setattr(dynamics, "rollout", counting)
+    p, x0, g = W.holo2d_circle(n=3, horizon=6, n_samples=5)
+    p = p.replace(n_steps=3)
+    mbd.plan(p, x0, g, iterations=2)
+    assert sum(calls) == 2 * 3 * 5 + 2
+
+
+def test_step_uses_the_specified_draws():
+    p, x0, g = W.holo2d_circle(n=3, horizon=5, n_samples=8)
+    p = p.replace(n_steps=4, seed=77)
+    D = p.D
+    out = mbd.denoise_step(p, x0, g, np.zeros(D), np.zeros(D), kappa=1, i=3)
+    assert np.array_equal(out["eps"], noise.draw(77, 0, 1, 3, 8, D))
+
+
+def test_planner_improves_circle_swap():
+    """Distribution-level sanity only (parity unpinned): one iteration on the
+    4-robot circle swap must beat the zero-control start and reach the goals."""
+    p, x0, g = W.holo2d_circle()
+    p = p.replace(n_samples=128)
+    u0 = np.zeros((p.n_robots, p.horizon, p.du))
+    base = mbd.apply_deformation(p, x0, g, u0, np.zeros(p.D))
+    u, hist = mbd.plan(p, x0, g, iterations=1)
+    assert hist[0]["r"] > base["r"] + 0.2
