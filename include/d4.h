@@ -1,0 +1,174 @@
+/*
+ * d4.h - C ABI of the MI355X (gfx950) denoising hot path of D4orm
+ * ("Multi-Robot Trajectories with Dynamics-aware Diffusion Denoised
+ * Deformations", Zhang et al., 2025).
+ *
+ * Conventions shared by every entry point:
+ *  - Every array argument is a DEVICE pointer unless marked "host".  The
+ *    caller allocates and owns it; the library never frees caller memory.
+ *  - Arrays are FP32 (int32 where stated), row-major, contiguous, and
+ *    4-byte aligned at least; index orders are given per argument.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls only enqueue work on it and return; results are ready once the
+ *    stream has synchronised.
+ *  - Return value: D4_OK or a negative status.  On error nothing was
+ *    enqueued, and d4_last_error() (thread-local) holds a message.  No C++
+ *    exception crosses this boundary.
+ *  - Device-side numerical failures (a non-finite reward) are reported in
+ *    d4_stats.status after the stream has synchronised.
+ *
+ * Symbols: n robots, T horizon steps (controls u[0..T-1], states x[0..T]),
+ * M Monte Carlo samples, N denoising steps, d_x/d_u/d_p state, control and
+ * position dimensions, D = n*T*d_u, element e = (k*T + t)*d_u + d.
+ */
+#ifndef D4_H
+#define D4_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    D4_OK = 0,
+    D4_EINVAL = -1,        /* bad argument, nothing enqueued */
+    D4_ENOMEM = -2,        /* device allocation failed */
+    D4_EHIP = -3,          /* a HIP runtime call failed */
+    D4_ENONFINITE = -4,    /* a reward was NaN or infinite (stats.status) */
+    D4_EUNSUPPORTED = -5   /* shape beyond this build's limits */
+};
+
+/* Robot models (Section V; the unicycle is the 3-state differential drive). */
+enum { D4_HOLO2D = 0, D4_HOLO3D = 1, D4_UNICYCLE = 2 };
+
+/* Flag bits of d4_problem.flags. */
+enum {
+    D4_NORMALIZE = 1,   /* z-score the batch rewards before the softmax */
+    D4_SAFE_PAIRS = 2   /* r_safe = -(number of colliding partners) instead of -1 */
+};
+
+/*
+ * One planning problem and its sampler settings.  Problem data follow the
+ * problem definition of Section III (team size, radius R_a, dynamics, horizon,
+ * time step); reward weights follow Eq. generic-reward and the r_goal/r_safe
+ * definitions of Section IV-A; temperature and schedule follow Section IV-B
+ * and Algorithm 1.
+ */
+typedef struct d4_problem {
+    int32_t dyn;            /* D4_HOLO2D, D4_HOLO3D or D4_UNICYCLE */
+    int32_t n_robots;       /* n, 1..32 */
+    int32_t horizon;        /* T, >= 1 */
+    int32_t n_samples;      /* M, >= 1 */
+    int32_t n_steps;        /* N, 1..65535 */
+    float dt;               /* > 0 */
+    float robot_radius;     /* R_a >= 0: safety condition uses 2 R_a */
+    float safety_margin;    /* epsilon >= 0: r_safe uses 2 R_a + epsilon */
+    float w_safe;           /* weight of r_safe */
+    float temperature;      /* lambda > 0 */
+    float beta_min;         /* linear beta schedule, step 1 */
+    float beta_max;         /* linear beta schedule, step N */
+    float u_lo[3];          /* per-component control box */
+    float u_hi[3];
+    float v_max;            /* per-component speed bound, holonomic models */
+    float goal_tol;         /* terminal-condition tolerance */
+    float d0_floor;         /* floor of the r_goal denominator */
+    uint32_t flags;         /* D4_NORMALIZE | D4_SAFE_PAIRS */
+    uint32_t instance_id;   /* fourth Philox counter word */
+    uint64_t seed;          /* Philox key */
+} d4_problem;
+
+/* Outcome of one iteration, written by d4_denoise_iter (host memory). */
+typedef struct d4_stats {
+    float reward;           /* r(tau) of the updated plan (Eq. generic-reward) */
+    float objective;        /* Eq. objective: fraction of robot-steps at the goal */
+    int32_t hits;           /* colliding pairs (reward threshold) summed over t */
+    int32_t robots_hit;     /* robot-steps with r_safe != 0 */
+    int32_t success;        /* safety (> 2 R_a) at every step and terminal condition */
+    int32_t status;         /* D4_OK or D4_ENONFINITE */
+} d4_stats;
+
+typedef struct d4_ctx d4_ctx;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* d4_last_error(void);
+
+/*
+ * Standard normal draws of one denoising step (the sampling step of
+ * Algorithm 1, Eq. mc).  eps[e][m], e < D, m < M, [D][M] layout.
+ * Counter-based Philox4x32-10 with key (lo32(seed), hi32(seed)) and counter
+ * (e>>2, m, (iter<<16)|step, instance_id); words pair into Box-Muller
+ * normals with an FP32 ln and sin/cos evaluated one correctly rounded
+ * operation at a time, so every implementation of the recipe draws the same
+ * bits.  iter < 65536, 1 <= step < 65536.
+ */
+int32_t d4_noise(const d4_problem* p, uint32_t iter, uint32_t step, float* eps, void* stream);
+
+/*
+ * Rollout (Section III feasibility, Section IV-C): x[m][k][0] = x0[k];
+ * x[m][k][t+1] = RK4(x[m][k][t], clip(u[m][k][t])) with holonomic speeds
+ * clipped per component after each step.
+ * x0 [n][d_x], u [M][n][T][d_u], x [M][n][T+1][d_x] (written).
+ */
+int32_t d4_rollout(const d4_problem* p, const float* x0, const float* u, float* x, void* stream);
+
+/*
+ * Team reward of trajectories (Eq. generic-reward with r_goal and r_safe of
+ * Section IV-A).  x [M][n][T+1][d_x], goal [n][d_p]; writes r [M],
+ * hits [M] (colliding pairs k<l summed over t=1..T, FP32 predicate
+ * ((dx*dx + dy*dy) + dz*dz) <= RN32((2 R_a + epsilon)^2)), and, unless NULL,
+ * robots_hit [M] (robot-steps with r_safe != 0).
+ */
+int32_t d4_fitness(const d4_problem* p, const float* x, const float* goal, float* r,
+                   int32_t* hits, int32_t* robots_hit, void* stream);
+
+/*
+ * Fused sampling + rollout + reward of denoising step `step` (Algorithm 1,
+ * sample and rollout steps, in the deformation form of Section IV-D):
+ * draws eps as d4_noise, forms Delta U^(m) = du_in / sqrt(abar_step)
+ * + sqrt(1/abar_step - 1) eps^(m), rolls out clip(u_base + Delta U^(m)) and
+ * scores it.  x0 [n][d_x], goal [n][d_p], u_base [D], du_in [D];
+ * writes eps [D][M], r [M], hits [M].
+ */
+int32_t d4_sample_rollout_fitness(const d4_problem* p, const float* x0, const float* goal,
+                                  const float* u_base, const float* du_in, uint32_t iter,
+                                  uint32_t step, float* eps, float* r, int32_t* hits,
+                                  void* stream);
+
+/*
+ * Softmax weights and the one-step update (Eq. mc and Eq. mbd-denoising,
+ * Algorithm 1 MC-estimate and denoise steps) for step `step`:
+ * w = softmax(normalise(r) / lambda), S[e] = sum_m w[m] eps[e][m],
+ * du_out[e] = sqrt(abar_{step-1}) (du_in[e] / sqrt(abar_step)
+ * + sqrt(1/abar_step - 1) S[e]).  r [M], eps [D][M], du_in [D] -> du_out [D];
+ * w_out [M] unless NULL.  du_out must not alias du_in.
+ */
+int32_t d4_score_update(const d4_problem* p, const float* r, const float* eps,
+                        const float* du_in, int32_t step, float* du_out, float* w_out,
+                        void* stream);
+
+/*
+ * Library-owned workspace for d4_denoise_iter: eps [D][M], r, hits, w,
+ * the Delta U ping-pong, stats and the captured HIP graph.  The shape
+ * (dyn, n, T, M, N) of later calls must match the one it was created for.
+ */
+int32_t d4_ctx_create(const d4_problem* p, d4_ctx** ctx);
+int32_t d4_ctx_destroy(d4_ctx* ctx);
+
+/*
+ * One iteration of Algorithm 2: Delta U_N = 0, denoising steps N..1 of
+ * Algorithm 1, then u_base <- clip(u_base + Delta U_0) and a rollout of the
+ * updated plan.  x0 [n][d_x], goal [n][d_p], u_base [n][T][d_u] (read and
+ * written); traj_out [n][T+1][d_x] unless NULL; stats (host memory, pinned
+ * for a truly asynchronous call) unless NULL.  The N steps replay one HIP
+ * graph captured on the first call.  Calls on one ctx must not overlap.
+ */
+int32_t d4_denoise_iter(d4_ctx* ctx, const d4_problem* p, const float* x0, const float* goal,
+                        float* u_base, uint32_t iter, float* traj_out, d4_stats* stats,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* D4_H */

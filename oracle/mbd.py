@@ -70,6 +70,20 @@ def effective_controls(prob, u_base, samples):
     return dynamics.clip_controls(prob, u)
 
 
+def sample_rewards(prob, x0, goal, u_base, du_i, kappa, i, sched=None, samples=None):
+    """Sampling, rollout and reward of step i for all samples or the listed ones."""
+    if sched is None:
+        sched = schedule.step_scalars(prob.n_steps, prob.beta_min, prob.beta_max)
+    ms, sg, _ = sched
+    D = prob.n_robots * prob.horizon * dynamics.dims(prob.dyn)[1]
+    eps = noise.draw(prob.seed, prob.instance_id, kappa, i, prob.n_samples, D, samples)
+    dev = sample_deformations(du_i, eps, ms[i], sg[i])
+    u = effective_controls(prob, u_base, dev)
+    x = dynamics.rollout(prob, x0, u)
+    r, hits, robots_hit = fitness.reward(prob, x, goal)
+    return dict(eps=eps, x=x, r=r, hits=hits, robots_hit=robots_hit)
+
+
 def denoise_step(prob, x0, goal, u_base, du_i, kappa, i, eps=None, sched=None, pred_dtype=np.float64):
     """One step of Algorithm 1 at index i; returns a dict with every intermediate."""
     if sched is None:

@@ -150,10 +150,11 @@ def normals_from_block(w0, w1, w2, w3):
     return z0, z1, z2, z3
 
 
-def draw(seed, instance_id, kappa, step, n_samples, dim):
+def draw(seed, instance_id, kappa, step, n_samples, dim, samples=None):
     """epsilon[e][m] for e < dim, m < n_samples at denoising step i of iteration kappa.
 
-    Returns an FP32 array of shape [dim][n_samples] (samples contiguous).
+    Returns an FP32 array of shape [dim][n_samples] (samples contiguous), or
+    [dim][len(samples)] for the listed sample indices only.
     """
     if not (0 <= kappa < 65536 and 0 <= step < 65536):
         raise ValueError("iteration and step must fit 16 bits")
@@ -161,10 +162,11 @@ def draw(seed, instance_id, kappa, step, n_samples, dim):
     k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
     groups = (dim + 3) // 4
     g = np.arange(groups, dtype=np.uint64)[:, None]
-    m = np.arange(n_samples, dtype=np.uint64)[None, :]
+    midx = np.arange(n_samples) if samples is None else np.asarray(samples)
+    m = midx.astype(np.uint64)[None, :]
     c2 = (int(kappa) << 16) | int(step)
     w = philox4x32_10(g, m, np.uint64(c2), np.uint64(int(instance_id)), k0, k1)
-    w = [np.broadcast_to(x, (groups, n_samples)) for x in w]
+    w = [np.broadcast_to(x, (groups, m.shape[1])) for x in w]
     z = normals_from_block(*w)
-    out = np.stack(z, axis=1).reshape(groups * 4, n_samples)
+    out = np.stack(z, axis=1).reshape(groups * 4, m.shape[1])
     return np.ascontiguousarray(out[:dim])

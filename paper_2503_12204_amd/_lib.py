@@ -1,0 +1,235 @@
+"""ctypes binding of libd4.so (include/d4.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Torch tensors supply device memory and the current HIP stream.
+If the library is missing this module raises at import time; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int32, c_uint32, c_uint64, c_void_p
+
+import torch
+
+from .workloads import Problem
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libd4.so")
+
+D4_OK, D4_EINVAL, D4_ENOMEM, D4_EHIP, D4_ENONFINITE, D4_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+
+class D4Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"d4 error {code}: {msg}")
+        self.code = code
+
+
+class D4Problem(ctypes.Structure):
+    _fields_ = [
+        ("dyn", c_int32), ("n_robots", c_int32), ("horizon", c_int32), ("n_samples", c_int32),
+        ("n_steps", c_int32), ("dt", c_float), ("robot_radius", c_float), ("safety_margin", c_float),
+        ("w_safe", c_float), ("temperature", c_float), ("beta_min", c_float), ("beta_max", c_float),
+        ("u_lo", c_float * 3), ("u_hi", c_float * 3), ("v_max", c_float), ("goal_tol", c_float),
+        ("d0_floor", c_float), ("flags", c_uint32), ("instance_id", c_uint32), ("seed", c_uint64),
+    ]
+
+
+class D4Stats(ctypes.Structure):
+    _fields_ = [("reward", c_float), ("objective", c_float), ("hits", c_int32),
+                ("robots_hit", c_int32), ("success", c_int32), ("status", c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_12204_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = POINTER(D4Problem)
+    fp = c_void_p
+    sig = {
+        "d4_last_error": ([], ctypes.c_char_p),
+        "d4_noise": ([P, c_uint32, c_uint32, fp, c_void_p], c_int32),
+        "d4_rollout": ([P, fp, fp, fp, c_void_p], c_int32),
+        "d4_fitness": ([P, fp, fp, fp, fp, fp, c_void_p], c_int32),
+        "d4_sample_rollout_fitness": ([P, fp, fp, fp, fp, c_uint32, c_uint32, fp, fp, fp, c_void_p], c_int32),
+        "d4_score_update": ([P, fp, fp, fp, c_int32, fp, fp, c_void_p], c_int32),
+        "d4_ctx_create": ([P, POINTER(c_void_p)], c_int32),
+        "d4_ctx_destroy": ([c_void_p], c_int32),
+        "d4_denoise_iter": ([c_void_p, P, fp, fp, fp, c_uint32, fp, POINTER(D4Stats), c_void_p], c_int32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc != D4_OK:
+        raise D4Error(rc, _lib.d4_last_error().decode())
+
+
+def to_c(p: Problem) -> D4Problem:
+    c = D4Problem()
+    for f in ("dyn", "n_robots", "horizon", "n_samples", "n_steps", "flags", "instance_id", "seed"):
+        setattr(c, f, int(getattr(p, f)))
+    for f in ("dt", "robot_radius", "safety_margin", "w_safe", "temperature", "beta_min", "beta_max",
+              "v_max", "goal_tol", "d0_floor"):
+        setattr(c, f, float(getattr(p, f)))
+    for i in range(3):
+        c.u_lo[i] = float(p.u_lo[i])
+        c.u_hi[i] = float(p.u_hi[i])
+    return c
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, shape=None, dtype=torch.float32, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return c_void_p(t.data_ptr())
+
+
+def _f32(a, device="cuda"):
+    return torch.as_tensor(a, dtype=torch.float32, device=device).contiguous()
+
+
+# ------------------------------------------------------------------ calls
+def noise(p: Problem, iteration: int, step: int, out=None):
+    """eps [D][M] of denoising step `step` of iteration `iteration`."""
+    c = to_c(p)
+    eps = out if out is not None else torch.empty((p.D, p.n_samples), dtype=torch.float32, device="cuda")
+    _check(_lib.d4_noise(ctypes.byref(c), iteration, step, _dev(eps, (p.D, p.n_samples), name="eps"), _stream()))
+    return eps
+
+
+def rollout(p: Problem, x0, u):
+    """x [M][n][T+1][d_x] from x0 [n][d_x] and controls u [M][n][T][d_u]."""
+    c = to_c(p)
+    M = u.shape[0]
+    q = p.replace(n_samples=M)
+    c = to_c(q)
+    x = torch.empty((M, p.n_robots, p.horizon + 1, p.dx), dtype=torch.float32, device="cuda")
+    _check(_lib.d4_rollout(ctypes.byref(c), _dev(x0, (p.n_robots, p.dx), name="x0"),
+                           _dev(u, (M, p.n_robots, p.horizon, p.du), name="u"), _dev(x, name="x"), _stream()))
+    return x
+
+
+def fitness(p: Problem, x, goal):
+    """(r [M], hits [M], robots_hit [M]) of trajectories x [M][n][T+1][d_x]."""
+    M = x.shape[0]
+    c = to_c(p.replace(n_samples=M))
+    r = torch.empty(M, dtype=torch.float32, device="cuda")
+    hits = torch.empty(M, dtype=torch.int32, device="cuda")
+    rh = torch.empty(M, dtype=torch.int32, device="cuda")
+    _check(_lib.d4_fitness(ctypes.byref(c), _dev(x, (M, p.n_robots, p.horizon + 1, p.dx), name="x"),
+                           _dev(goal, (p.n_robots, p.dp), name="goal"), _dev(r), _dev(hits, dtype=torch.int32),
+                           _dev(rh, dtype=torch.int32), _stream()))
+    return r, hits, rh
+
+
+def sample_rollout_fitness(p: Problem, x0, goal, u_base, du_in, iteration: int, step: int,
+                           eps=None, r=None, hits=None):
+    """Fused sampling, rollout and reward of one denoising step -> (eps, r, hits)."""
+    c = to_c(p)
+    if eps is None:
+        eps = torch.empty((p.D, p.n_samples), dtype=torch.float32, device="cuda")
+    if r is None:
+        r = torch.empty(p.n_samples, dtype=torch.float32, device="cuda")
+    if hits is None:
+        hits = torch.empty(p.n_samples, dtype=torch.int32, device="cuda")
+    _check(_lib.d4_sample_rollout_fitness(
+        ctypes.byref(c), _dev(x0, (p.n_robots, p.dx), name="x0"), _dev(goal, (p.n_robots, p.dp), name="goal"),
+        _dev(u_base, (p.D,), name="u_base"), _dev(du_in, (p.D,), name="du_in"), iteration, step,
+        _dev(eps, (p.D, p.n_samples), name="eps"), _dev(r, (p.n_samples,), name="r"),
+        _dev(hits, (p.n_samples,), dtype=torch.int32, name="hits"), _stream()))
+    return eps, r, hits
+
+
+def score_update(p: Problem, r, eps, du_in, step: int, du_out=None, w_out=None):
+    """Softmax weights and the one-step update -> (du_out [D], w [M])."""
+    c = to_c(p)
+    if du_out is None:
+        du_out = torch.empty(p.D, dtype=torch.float32, device="cuda")
+    if w_out is None:
+        w_out = torch.empty(p.n_samples, dtype=torch.float32, device="cuda")
+    _check(_lib.d4_score_update(ctypes.byref(c), _dev(r, (p.n_samples,), name="r"),
+                                _dev(eps, (p.D, p.n_samples), name="eps"), _dev(du_in, (p.D,), name="du_in"),
+                                step, _dev(du_out, (p.D,), name="du_out"), _dev(w_out, (p.n_samples,), name="w"),
+                                _stream()))
+    return du_out, w_out
+
+
+class Context:
+    """Owns a d4_ctx (workspace + captured graph) for one problem shape."""
+
+    def __init__(self, p: Problem):
+        self.p = p
+        self._c = to_c(p)
+        h = c_void_p()
+        _check(_lib.d4_ctx_create(ctypes.byref(self._c), ctypes.byref(h)))
+        self._h = h
+        self._stats = D4Stats()
+
+    def close(self):
+        if self._h:
+            _lib.d4_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def denoise_iter(self, x0, goal, u_base, iteration: int, traj=None, sync=True, p: Problem = None):
+        """One iteration of Algorithm 2; u_base [n][T][d_u] is updated in place."""
+        if p is not None:
+            self._c = to_c(p)
+            self.p = p
+        p = self.p
+        tr = _dev(traj, (p.n_robots, p.horizon + 1, p.dx), name="traj") if traj is not None else None
+        _check(_lib.d4_denoise_iter(self._h, ctypes.byref(self._c), _dev(x0, (p.n_robots, p.dx), name="x0"),
+                                    _dev(goal, (p.n_robots, p.dp), name="goal"),
+                                    _dev(u_base, (p.n_robots, p.horizon, p.du), name="u_base"),
+                                    iteration, tr, ctypes.byref(self._stats) if sync else None, _stream()))
+        if not sync:
+            return None
+        torch.cuda.current_stream().synchronize()
+        s = self._stats
+        return dict(reward=s.reward, objective=s.objective, hits=s.hits, robots_hit=s.robots_hit,
+                    success=bool(s.success), status=s.status)
+
+
+def plan(p: Problem, x0, goal, iterations: int, u_init=None, stop_on_success=False):
+    """Algorithm 2 from zero controls (or u_init): returns (u [n][T][d_u], per-iteration stats)."""
+    x0 = _f32(x0)
+    goal = _f32(goal)
+    u = torch.zeros((p.n_robots, p.horizon, p.du), dtype=torch.float32, device="cuda") if u_init is None \
+        else _f32(u_init).reshape(p.n_robots, p.horizon, p.du).clone()
+    ctx = Context(p)
+    hist = []
+    try:
+        for k in range(iterations):
+            st = ctx.denoise_iter(x0, goal, u, k)
+            hist.append(st)
+            if stop_on_success and st["success"]:
+                break
+    finally:
+        ctx.close()
+    return u, hist

@@ -1,0 +1,586 @@
+// Host side of the C ABI declared in include/d4.h: argument validation, the
+// noise schedule, launch shapes, the per-problem workspace and the captured
+// HIP graph of one deformation iteration (Algorithm 2 loop body).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "d4.h"
+#include "d4_kernels.hpp"
+
+using namespace d4;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(D4_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+#define HIP_LAUNCH_CHECK(name)                                                         \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return fail(D4_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Shape {
+    int dx, du, dp;
+};
+
+Shape shape_of(int dyn) {
+    switch (dyn) {
+        case HOLO2D: return {4, 2, 2};
+        case HOLO3D: return {6, 3, 3};
+        default: return {3, 2, 2};
+    }
+}
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+int validate(const d4_problem* p) {
+    if (!p) return fail(D4_EINVAL, "problem is NULL");
+    if (p->dyn < 0 || p->dyn > 2) return fail(D4_EINVAL, "dyn %d is not a known model", p->dyn);
+    if (p->n_robots < 1 || p->n_robots > 32)
+        return fail(D4_EINVAL, "n_robots %d outside 1..32", p->n_robots);
+    if (p->horizon < 1) return fail(D4_EINVAL, "horizon %d < 1", p->horizon);
+    if (p->n_samples < 1) return fail(D4_EINVAL, "n_samples %d < 1", p->n_samples);
+    if (p->n_steps < 1 || p->n_steps > 65535)
+        return fail(D4_EINVAL, "n_steps %d outside 1..65535", p->n_steps);
+    if (!(p->dt > 0.0f) || !finite_f(p->dt)) return fail(D4_EINVAL, "dt must be positive");
+    if (!(p->temperature > 0.0f) || !finite_f(p->temperature))
+        return fail(D4_EINVAL, "temperature must be positive");
+    if (!(p->robot_radius >= 0.0f) || !(p->safety_margin >= 0.0f) || !finite_f(p->robot_radius) ||
+        !finite_f(p->safety_margin))
+        return fail(D4_EINVAL, "robot_radius and safety_margin must be >= 0");
+    if (!(p->d0_floor > 0.0f)) return fail(D4_EINVAL, "d0_floor must be positive");
+    if (!finite_f(p->w_safe) || !finite_f(p->beta_min) || !finite_f(p->beta_max))
+        return fail(D4_EINVAL, "non-finite weight or schedule");
+    if (!(p->beta_min > 0.0f) || !(p->beta_max < 1.0f) || p->beta_min > p->beta_max)
+        return fail(D4_EINVAL, "need 0 < beta_min <= beta_max < 1");
+    const Shape s = shape_of(p->dyn);
+    for (int d = 0; d < s.du; ++d)
+        if (!(p->u_lo[d] <= p->u_hi[d]) || !finite_f(p->u_lo[d]) || !finite_f(p->u_hi[d]))
+            return fail(D4_EINVAL, "control box %d is empty or non-finite", d);
+    if (p->dyn != UNICYCLE && !(p->v_max >= 0.0f)) return fail(D4_EINVAL, "v_max must be >= 0");
+    const double D = (double)p->n_robots * p->horizon * s.du;
+    if (D * p->n_samples > 4.0e9) return fail(D4_EUNSUPPORTED, "D*M = %.0f too large", D * p->n_samples);
+    if ((D + 3) / 4 > 65535.0) return fail(D4_EUNSUPPORTED, "D = %.0f too large for one launch", D);
+    return D4_OK;
+}
+
+int need(const void* ptr, const char* name) {
+    if (!ptr) return fail(D4_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(ptr) & 3u) return fail(D4_EINVAL, "%s is not 4-byte aligned", name);
+    return D4_OK;
+}
+
+#define NEED(ptr)                                \
+    do {                                         \
+        int rc_ = need((ptr), #ptr);             \
+        if (rc_) return rc_;                     \
+    } while (0)
+
+struct Schedule {
+    std::vector<float> ms, sigma, os;  // index 0..N
+};
+
+// Linear betas over i = 1..N (both ends included), alpha-bar products in FP64.
+Schedule make_schedule(const d4_problem* p) {
+    const int N = p->n_steps;
+    Schedule s;
+    s.ms.assign(N + 1, 0.0f);
+    s.sigma.assign(N + 1, 0.0f);
+    s.os.assign(N + 1, 0.0f);
+    double ab_prev = 1.0;
+    for (int i = 1; i <= N; ++i) {
+        const double beta = N == 1 ? (double)p->beta_min
+                                   : (double)p->beta_min +
+                                         ((double)p->beta_max - (double)p->beta_min) * (i - 1) / (N - 1);
+        const double ab = ab_prev * (1.0 - beta);
+        s.ms[i] = (float)(1.0 / std::sqrt(ab));
+        s.sigma[i] = (float)std::sqrt(1.0 / ab - 1.0);
+        s.os[i] = (float)std::sqrt(ab_prev);
+        ab_prev = ab;
+    }
+    return s;
+}
+
+float thr2_reward(const d4_problem* p) {
+    const double thr = 2.0 * (double)p->robot_radius + (double)p->safety_margin;
+    return (float)(thr * thr);
+}
+
+StepConsts step_consts(const d4_problem* p) {
+    StepConsts c;
+    c.dt = p->dt;
+    c.hdt = (float)(0.5 * p->dt);
+    c.hdt2 = (float)(0.5 * (double)p->dt * (double)p->dt);
+    c.dt6 = (float)((double)p->dt / 6.0);
+    c.vmax = p->v_max;
+    return c;
+}
+
+struct Tile {
+    int S, Tb;
+};
+
+// Samples per workgroup and time-block length of the reward kernels.
+Tile pick_tile(const d4_problem* p) {
+    const int n = p->n_robots;
+    int S = 64;
+    while (S > 1 && S * n > 256) S >>= 1;
+    const char* env = std::getenv("D4_TILE_S");
+    if (env) {
+        int v = std::atoi(env);
+        if (v >= 1 && v * n <= 1024) S = v;
+    }
+    int Tb = 4;
+    const char* envt = std::getenv("D4_TILE_TB");
+    if (envt) {
+        int v = std::atoi(envt);
+        if (v >= 1 && v <= 64) Tb = v;
+    }
+    return {S, Tb};
+}
+
+size_t rollfit_lds(const d4_problem* p, Tile t) {
+    const Shape s = shape_of(p->dyn);
+    const size_t n = p->n_robots;
+    const size_t a = (size_t)2 * t.Tb * s.dp * n * t.S + (size_t)2 * t.Tb * t.S;
+    const size_t b = (size_t)3 * n * t.S;
+    return 4 * (a > b ? a : b);
+}
+
+RollFitArgs base_args(const d4_problem* p, Tile tile) {
+    RollFitArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = p->n_robots;
+    a.T = p->horizon;
+    a.M = p->n_samples;
+    a.S = tile.S;
+    a.Tb = tile.Tb;
+    a.thr2 = thr2_reward(p);
+    a.w_safe = p->w_safe;
+    a.d0_floor = p->d0_floor;
+    for (int d = 0; d < 3; ++d) {
+        a.ulo[d] = p->u_lo[d];
+        a.uhi[d] = p->u_hi[d];
+    }
+    a.sc = step_consts(p);
+    a.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.inst = p->instance_id;
+    a.flags = p->flags;
+    return a;
+}
+
+template <bool FROM_X>
+int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStream_t st) {
+    const dim3 grid((p->n_samples + tile.S - 1) / tile.S);
+    const dim3 block(tile.S * p->n_robots);
+    const size_t lds = rollfit_lds(p, tile);
+    if (lds > 65536) return fail(D4_EUNSUPPORTED, "reward kernel needs %zu bytes of LDS", lds);
+    switch (p->dyn) {
+        case HOLO2D: hipLaunchKernelGGL((k_rollfit<HOLO2D, FROM_X>), grid, block, lds, st, a); break;
+        case HOLO3D: hipLaunchKernelGGL((k_rollfit<HOLO3D, FROM_X>), grid, block, lds, st, a); break;
+        default: hipLaunchKernelGGL((k_rollfit<UNICYCLE, FROM_X>), grid, block, lds, st, a); break;
+    }
+    HIP_LAUNCH_CHECK("k_rollfit");
+    return D4_OK;
+}
+
+int launch_softmax(const d4_problem* p, const float* r, float* w, int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_softmax, dim3(1), dim3(1024), 0, st, r, w, p->n_samples,
+                       1.0f / p->temperature, (int)(p->flags & FLAG_NORMALIZE), status);
+    HIP_LAUNCH_CHECK("k_softmax");
+    return D4_OK;
+}
+
+int launch_reduce(const d4_problem* p, const float* eps, const float* w, const float* du_in,
+                  float* du_out, float ms, float sigma, float os, hipStream_t st) {
+    const int D = p->n_robots * p->horizon * shape_of(p->dyn).du;
+    const int M = p->n_samples;
+    const bool vec = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(eps) & 15u) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(w) & 15u) == 0);
+    const bool staged = M <= 16384;
+    const int waves = 4;
+    int grid = (D + waves - 1) / waves;
+    if (grid > 1024) grid = 1024;
+    const size_t lds = staged ? (size_t)M * 4 : 0;
+    if (staged && vec)
+        hipLaunchKernelGGL((k_reduce_update<true, true>), dim3(grid), dim3(64 * waves), lds, st, eps, w,
+                           du_in, du_out, D, M, ms, sigma, os);
+    else if (staged)
+        hipLaunchKernelGGL((k_reduce_update<true, false>), dim3(grid), dim3(64 * waves), lds, st, eps, w,
+                           du_in, du_out, D, M, ms, sigma, os);
+    else if (vec)
+        hipLaunchKernelGGL((k_reduce_update<false, true>), dim3(grid), dim3(64 * waves), 0, st, eps, w,
+                           du_in, du_out, D, M, ms, sigma, os);
+    else
+        hipLaunchKernelGGL((k_reduce_update<false, false>), dim3(grid), dim3(64 * waves), 0, st, eps, w,
+                           du_in, du_out, D, M, ms, sigma, os);
+    HIP_LAUNCH_CHECK("k_reduce_update");
+    return D4_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct d4_ctx {
+    d4_problem prob;
+    bool captured;
+    int device;
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    float *eps, *r, *w, *du_a, *du_b, *x0, *goal, *ubase, *traj, *stats;
+    int* hits;
+    int* status;
+    uint32_t* iter;
+};
+
+namespace {
+
+void free_ctx_buffers(d4_ctx* c) {
+    float* fb[] = {c->eps, c->r, c->w, c->du_a, c->du_b, c->x0, c->goal, c->ubase, c->traj, c->stats};
+    for (float* f : fb)
+        if (f) (void)hipFree(f);
+    if (c->hits) (void)hipFree(c->hits);
+    if (c->status) (void)hipFree(c->status);
+    if (c->iter) (void)hipFree(c->iter);
+}
+
+bool same_problem(const d4_problem& a, const d4_problem& b) {
+    return std::memcmp(&a, &b, sizeof(d4_problem)) == 0;
+}
+
+bool same_shape(const d4_problem& a, const d4_problem& b) {
+    return a.dyn == b.dyn && a.n_robots == b.n_robots && a.horizon == b.horizon &&
+           a.n_samples == b.n_samples && a.n_steps == b.n_steps;
+}
+
+// Enqueue one full iteration on `st` using only ctx-owned buffers.
+int enqueue_iteration(d4_ctx* c, hipStream_t st) {
+    const d4_problem* p = &c->prob;
+    const Shape s = shape_of(p->dyn);
+    const int D = p->n_robots * p->horizon * s.du;
+    const Schedule sc = make_schedule(p);
+    const Tile tile = pick_tile(p);
+    hipLaunchKernelGGL(k_fill, dim3((D + 255) / 256), dim3(256), 0, st, c->du_a, D, 0.0f);
+    HIP_LAUNCH_CHECK("k_fill");
+    float* du_cur = c->du_a;
+    float* du_nxt = c->du_b;
+    RollFitArgs a = base_args(p, tile);
+    a.x0 = c->x0;
+    a.goal = c->goal;
+    a.u_base = c->ubase;
+    a.eps = c->eps;
+    a.r = c->r;
+    a.hits = c->hits;
+    a.robots_hit = nullptr;
+    a.iter_dev = c->iter;
+    for (int i = p->n_steps; i >= 1; --i) {
+        a.du_in = du_cur;
+        a.step = (uint32_t)i;
+        a.mean_scale = sc.ms[i];
+        a.sigma = sc.sigma[i];
+        int rc = launch_rollfit<false>(p, a, tile, st);
+        if (rc) return rc;
+        rc = launch_softmax(p, c->r, c->w, c->status, st);
+        if (rc) return rc;
+        rc = launch_reduce(p, c->eps, c->w, du_cur, du_nxt, sc.ms[i], sc.sigma[i], sc.os[i], st);
+        if (rc) return rc;
+        float* t = du_cur;
+        du_cur = du_nxt;
+        du_nxt = t;
+    }
+    FinalArgs f;
+    std::memset(&f, 0, sizeof f);
+    f.u_base = c->ubase;
+    f.du0 = du_cur;
+    f.x0 = c->x0;
+    f.goal = c->goal;
+    f.traj = c->traj;
+    f.stats = c->stats;
+    f.status = c->status;
+    f.n = p->n_robots;
+    f.T = p->horizon;
+    for (int d = 0; d < 3; ++d) {
+        f.ulo[d] = p->u_lo[d];
+        f.uhi[d] = p->u_hi[d];
+    }
+    f.sc = step_consts(p);
+    f.thr2 = thr2_reward(p);
+    const double s2 = 2.0 * (double)p->robot_radius;
+    f.safe2 = (float)(s2 * s2);
+    f.goal_tol = p->goal_tol;
+    f.w_safe = p->w_safe;
+    f.d0_floor = p->d0_floor;
+    f.flags = p->flags;
+    switch (p->dyn) {
+        case HOLO2D: hipLaunchKernelGGL(k_apply_final<HOLO2D>, dim3(1), dim3(256), 0, st, f); break;
+        case HOLO3D: hipLaunchKernelGGL(k_apply_final<HOLO3D>, dim3(1), dim3(256), 0, st, f); break;
+        default: hipLaunchKernelGGL(k_apply_final<UNICYCLE>, dim3(1), dim3(256), 0, st, f); break;
+    }
+    HIP_LAUNCH_CHECK("k_apply_final");
+    return D4_OK;
+}
+
+bool graphs_disabled() {
+    const char* e = std::getenv("D4_NO_GRAPH");
+    return e && e[0] == '1';
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* d4_last_error(void) { return g_err.c_str(); }
+
+int32_t d4_noise(const d4_problem* p, uint32_t iter, uint32_t step, float* eps, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    NEED(eps);
+    if (iter > 65535u || step < 1u || step > 65535u)
+        return fail(D4_EINVAL, "iter %u / step %u outside the 16-bit counter fields", iter, step);
+    const int D = p->n_robots * p->horizon * shape_of(p->dyn).du;
+    const int M = p->n_samples;
+    const dim3 grid((M + 255) / 256, (D + 3) / 4);
+    hipLaunchKernelGGL(k_noise, grid, dim3(256), 0, (hipStream_t)stream, eps, D, M,
+                       (iter << 16) | step, p->instance_id, (uint32_t)(p->seed & 0xFFFFFFFFull),
+                       (uint32_t)(p->seed >> 32));
+    HIP_LAUNCH_CHECK("k_noise");
+    return D4_OK;
+}
+
+int32_t d4_rollout(const d4_problem* p, const float* x0, const float* u, float* x, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    NEED(x0);
+    NEED(u);
+    NEED(x);
+    const int total = p->n_samples * p->n_robots;
+    const dim3 grid((total + 255) / 256);
+    const StepConsts sc = step_consts(p);
+    hipStream_t st = (hipStream_t)stream;
+#define D4_ROLL(DY)                                                                              \
+    hipLaunchKernelGGL(k_rollout<DY>, grid, dim3(256), 0, st, x0, u, x, p->n_robots, p->horizon, \
+                       p->n_samples, sc, p->u_lo[0], p->u_lo[1], p->u_lo[2], p->u_hi[0],         \
+                       p->u_hi[1], p->u_hi[2])
+    switch (p->dyn) {
+        case HOLO2D: D4_ROLL(HOLO2D); break;
+        case HOLO3D: D4_ROLL(HOLO3D); break;
+        default: D4_ROLL(UNICYCLE); break;
+    }
+#undef D4_ROLL
+    HIP_LAUNCH_CHECK("k_rollout");
+    return D4_OK;
+}
+
+int32_t d4_fitness(const d4_problem* p, const float* x, const float* goal, float* r, int32_t* hits,
+                   int32_t* robots_hit, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    NEED(x);
+    NEED(goal);
+    NEED(r);
+    NEED(hits);
+    if (robots_hit) NEED(robots_hit);
+    const Tile tile = pick_tile(p);
+    RollFitArgs a = base_args(p, tile);
+    a.xs = x;
+    a.goal = goal;
+    a.r = r;
+    a.hits = hits;
+    a.robots_hit = robots_hit;
+    return launch_rollfit<true>(p, a, tile, (hipStream_t)stream);
+}
+
+int32_t d4_sample_rollout_fitness(const d4_problem* p, const float* x0, const float* goal,
+                                  const float* u_base, const float* du_in, uint32_t iter,
+                                  uint32_t step, float* eps, float* r, int32_t* hits, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    NEED(x0);
+    NEED(goal);
+    NEED(u_base);
+    NEED(du_in);
+    NEED(eps);
+    NEED(r);
+    NEED(hits);
+    if (iter > 65535u || step < 1u || step > (uint32_t)p->n_steps)
+        return fail(D4_EINVAL, "iter %u or step %u out of range", iter, step);
+    const Schedule sc = make_schedule(p);
+    const Tile tile = pick_tile(p);
+    RollFitArgs a = base_args(p, tile);
+    a.x0 = x0;
+    a.goal = goal;
+    a.u_base = u_base;
+    a.du_in = du_in;
+    a.eps = eps;
+    a.r = r;
+    a.hits = hits;
+    a.iter = iter;
+    a.step = step;
+    a.mean_scale = sc.ms[step];
+    a.sigma = sc.sigma[step];
+    return launch_rollfit<false>(p, a, tile, (hipStream_t)stream);
+}
+
+int32_t d4_score_update(const d4_problem* p, const float* r, const float* eps, const float* du_in,
+                        int32_t step, float* du_out, float* w_out, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    NEED(r);
+    NEED(eps);
+    NEED(du_in);
+    NEED(du_out);
+    if (step < 1 || step > p->n_steps) return fail(D4_EINVAL, "step %d outside 1..N", step);
+    if (du_out == du_in) return fail(D4_EINVAL, "du_out must not alias du_in");
+    hipStream_t st = (hipStream_t)stream;
+    float* w = w_out;
+    if (w) NEED(w);
+    if (!w) {
+        // weights are needed by the reduction; use a transient buffer
+        HIP_TRY(hipMallocAsync((void**)&w, sizeof(float) * (size_t)p->n_samples, st));
+    }
+    const Schedule sc = make_schedule(p);
+    rc = launch_softmax(p, r, w, nullptr, st);
+    if (!rc) rc = launch_reduce(p, eps, w, du_in, du_out, sc.ms[step], sc.sigma[step], sc.os[step], st);
+    if (!w_out) (void)hipFreeAsync(w, st);
+    return rc;
+}
+
+int32_t d4_ctx_create(const d4_problem* p, d4_ctx** out) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!out) return fail(D4_EINVAL, "ctx out-pointer is NULL");
+    d4_ctx* c = new (std::nothrow) d4_ctx;
+    if (!c) return fail(D4_ENOMEM, "host allocation failed");
+    std::memset(c, 0, sizeof *c);
+    c->prob = *p;
+    HIP_TRY(hipGetDevice(&c->device));
+    const Shape s = shape_of(p->dyn);
+    const size_t n = p->n_robots, T = p->horizon, M = p->n_samples;
+    const size_t D = n * T * s.du;
+    struct {
+        void** ptr;
+        size_t bytes;
+    } allocs[] = {
+        {(void**)&c->eps, 4 * D * M}, {(void**)&c->r, 4 * M},       {(void**)&c->w, 4 * M},
+        {(void**)&c->du_a, 4 * D},    {(void**)&c->du_b, 4 * D},    {(void**)&c->x0, 4 * n * s.dx},
+        {(void**)&c->goal, 4 * n * s.dp}, {(void**)&c->ubase, 4 * D}, {(void**)&c->traj, 4 * n * (T + 1) * s.dx},
+        {(void**)&c->stats, sizeof(d4_stats)}, {(void**)&c->hits, 4 * M}, {(void**)&c->status, 4},
+        {(void**)&c->iter, 4},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
+            free_ctx_buffers(c);
+            delete c;
+            return fail(D4_ENOMEM, "hipMalloc of %zu bytes failed", a.bytes);
+        }
+    }
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        free_ctx_buffers(c);
+        delete c;
+        return fail(D4_EHIP, "stream creation failed");
+    }
+    *out = c;
+    return D4_OK;
+}
+
+int32_t d4_ctx_destroy(d4_ctx* c) {
+    if (!c) return D4_OK;
+    (void)hipDeviceSynchronize();
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    free_ctx_buffers(c);
+    delete c;
+    return D4_OK;
+}
+
+int32_t d4_denoise_iter(d4_ctx* c, const d4_problem* p, const float* x0, const float* goal,
+                        float* u_base, uint32_t iter, float* traj_out, d4_stats* stats,
+                        void* stream) {
+    if (!c) return fail(D4_EINVAL, "ctx is NULL");
+    int rc = validate(p);
+    if (rc) return rc;
+    NEED(x0);
+    NEED(goal);
+    NEED(u_base);
+    if (traj_out) NEED(traj_out);
+    if (iter > 65535u) return fail(D4_EINVAL, "iter %u does not fit 16 bits", iter);
+    if (!same_shape(*p, c->prob)) return fail(D4_EINVAL, "problem shape differs from the ctx's");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != c->device) return fail(D4_EINVAL, "ctx was created on device %d, current is %d", c->device, dev);
+    hipStream_t st = (hipStream_t)stream;
+    if (!same_problem(*p, c->prob)) {
+        // scalars baked into the graph changed: capture again
+        c->prob = *p;
+        if (c->exec) (void)hipGraphExecDestroy(c->exec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->exec = nullptr;
+        c->graph = nullptr;
+        c->captured = false;
+    }
+    const Shape s = shape_of(p->dyn);
+    const size_t n = p->n_robots, T = p->horizon;
+    const size_t D = n * T * s.du;
+    HIP_TRY(hipMemcpyAsync(c->x0, x0, 4 * n * s.dx, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->goal, goal, 4 * n * s.dp, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->ubase, u_base, 4 * D, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, st, c->iter, iter, c->status);
+    HIP_LAUNCH_CHECK("k_set_iter");
+    if (graphs_disabled()) {
+        rc = enqueue_iteration(c, st);
+        if (rc) return rc;
+    } else {
+        if (!c->captured) {
+            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_iteration(c, c->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (ec != hipSuccess) return fail(D4_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+            c->graph = g;
+            HIP_TRY(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+            c->captured = true;
+        }
+        HIP_TRY(hipGraphLaunch(c->exec, st));
+    }
+    HIP_TRY(hipMemcpyAsync(u_base, c->ubase, 4 * D, hipMemcpyDeviceToDevice, st));
+    if (traj_out)
+        HIP_TRY(hipMemcpyAsync(traj_out, c->traj, 4 * n * (T + 1) * s.dx, hipMemcpyDeviceToDevice, st));
+    if (stats) HIP_TRY(hipMemcpyAsync(stats, c->stats, sizeof(d4_stats), hipMemcpyDeviceToHost, st));
+    return D4_OK;
+}
+
+}  // extern "C"

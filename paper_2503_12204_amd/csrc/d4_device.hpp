@@ -1,0 +1,231 @@
+// Device math of the denoising hot path (gfx950, wave64).
+//
+//  - Counter-based normal draws for the sampling step of Algorithm 1
+//    (Eq. mc): Philox4x32-10 (Salmon et al., SC'11) feeding a Box-Muller
+//    transform whose ln and sin/cos are evaluated in FP32 one correctly
+//    rounded operation at a time (no contraction), so the draws are the
+//    same bits on every implementation of the recipe.
+//  - RK4 steps of the three robot models (Section III feasibility condition,
+//    Section V models).  The double integrator's RK4 step is evaluated in
+//    its exact closed form p + v dt + a dt^2/2, v + a dt (RK4 is exact when
+//    A^2 = 0); the unicycle's RK4 step is evaluated as Simpson's rule on the
+//    heading, which is what the four stages reduce to when theta is linear
+//    in time, with the end-of-step sine/cosine reused as the next step's
+//    first stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace d4 {
+
+enum { HOLO2D = 0, HOLO3D = 1, UNICYCLE = 2 };
+enum { FLAG_NORMALIZE = 1, FLAG_SAFE_PAIRS = 2 };
+
+// ------------------------------------------------------------------ Philox
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+// ------------------------------------------------ FP32 ln and sin/cos recipe
+// Natural log of a uniform in (0, 1): u = 2^e f, f in [0.75, 1.5),
+// ln f = 2 atanh(s), s = (f - 1)/(f + 1), atanh by its Taylor series in
+// Horner form through s^11, e*ln2 split as 355/512 plus the FP32 remainder.
+__device__ __forceinline__ float ln_unit(float u) {
+#pragma clang fp contract(off)
+    const float A3 = 1.0f / 3.0f, A5 = 1.0f / 5.0f, A7 = 1.0f / 7.0f, A9 = 1.0f / 9.0f,
+                A11 = 1.0f / 11.0f;
+    const float LN2_HI = 355.0f / 512.0f;
+    const float LN2_LO = (float)(0.693147180559945309417232121458 - 355.0 / 512.0);
+    const uint32_t b = __float_as_uint(u);
+    int e = (int)(b >> 23) - 127;
+    float f = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
+    if (f >= 1.5f) {
+        f = f * 0.5f;
+        e += 1;
+    }
+    const float s = (f - 1.0f) / (f + 1.0f);
+    const float s2 = s * s;
+    float q = A11 * s2 + A9;
+    q = q * s2 + A7;
+    q = q * s2 + A5;
+    q = q * s2 + A3;
+    const float t = s + s * (s2 * q);
+    const float lnf = 2.0f * t;
+    const float ef = (float)e;
+    const float hi = ef * LN2_HI;
+    const float lo = ef * LN2_LO;
+    return hi + (lnf + lo);
+}
+
+// sin and cos of 2 pi u_b for u_b = (2j + 1) 2^-24, j = word >> 9: exact
+// quarter-turn reduction in integers, then Taylor series on [-pi/4, pi/4].
+__device__ __forceinline__ void sincos_2pi_word(uint32_t word, float& sn_o, float& cs_o) {
+#pragma clang fp contract(off)
+    const float S3 = -1.0f / 6.0f, S5 = 1.0f / 120.0f, S7 = -1.0f / 5040.0f,
+                S9 = 1.0f / 362880.0f, S11 = -1.0f / 39916800.0f;
+    const float C2 = -1.0f / 2.0f, C4 = 1.0f / 24.0f, C6 = -1.0f / 720.0f, C8 = 1.0f / 40320.0f,
+                C10 = -1.0f / 3628800.0f, C12 = 1.0f / 479001600.0f;
+    const float PI_F = 3.14159265358979323846f;
+    const int jj = (int)((word >> 9) << 1) + 1;
+    const int q = (jj + (1 << 21)) >> 22;
+    const int rn = jj - (q << 22);
+    const float r = (float)rn * 0x1.0p-23f;
+    const float y = r * PI_F;
+    const float y2 = y * y;
+    float sp = S11 * y2 + S9;
+    sp = sp * y2 + S7;
+    sp = sp * y2 + S5;
+    sp = sp * y2 + S3;
+    const float sn = y + y * (y2 * sp);
+    float cp = C12 * y2 + C10;
+    cp = cp * y2 + C8;
+    cp = cp * y2 + C6;
+    cp = cp * y2 + C4;
+    cp = cp * y2 + C2;
+    const float cs = 1.0f + y2 * cp;
+    const int qq = q & 3;
+    sn_o = qq == 0 ? sn : qq == 1 ? cs : qq == 2 ? -sn : -cs;
+    cs_o = qq == 0 ? cs : qq == 1 ? -sn : qq == 2 ? -cs : sn;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z_even, float& z_odd) {
+#pragma clang fp contract(off)
+    const float u = (float)(((wa >> 9) << 1) + 1u) * 0x1.0p-24f;
+    const float rho = __builtin_sqrtf(-2.0f * ln_unit(u));
+    float s, c;
+    sincos_2pi_word(wb, s, c);
+    z_even = rho * c;
+    z_odd = rho * s;
+}
+
+// The four normals of Philox block `group` for sample m.
+__device__ __forceinline__ void normal_block(uint32_t group, uint32_t m, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1, float& z0, float& z1,
+                                             float& z2, float& z3) {
+    uint32_t w0 = group, w1 = m, w2 = c2, w3 = c3;
+    philox4x32_10(w0, w1, w2, w3, k0, k1);
+    box_muller(w0, w1, z0, z1);
+    box_muller(w2, w3, z2, z3);
+}
+
+// Streams the normals of consecutive elements e of one sample; a block is
+// generated when the element index crosses into it.
+struct NormalStream {
+    uint32_t group;
+    float z0, z1, z2, z3;
+    uint32_t m, c2, c3, k0, k1;
+
+    __device__ __forceinline__ void init(uint32_t m_, uint32_t c2_, uint32_t c3_, uint32_t k0_,
+                                         uint32_t k1_) {
+        group = 0xFFFFFFFFu;
+        z0 = z1 = z2 = z3 = 0.0f;
+        m = m_;
+        c2 = c2_;
+        c3 = c3_;
+        k0 = k0_;
+        k1 = k1_;
+    }
+    __device__ __forceinline__ float get(uint32_t e) {
+        const uint32_t g = e >> 2;
+        if (g != group) {
+            group = g;
+            normal_block(g, m, c2, c3, k0, k1, z0, z1, z2, z3);
+        }
+        const uint32_t j = e & 3u;
+        return j == 0 ? z0 : j == 1 ? z1 : j == 2 ? z2 : z3;
+    }
+};
+
+// ---------------------------------------------------------------- dynamics
+struct StepConsts {
+    float dt, hdt, hdt2, dt6, vmax;
+};
+
+template <int DYN>
+struct Dyn;
+
+template <>
+struct Dyn<HOLO2D> {
+    static constexpr int DX = 4, DU = 2, DP = 2, AUX = 1;
+    __device__ __forceinline__ static void init(const float*, float*) {}
+    __device__ __forceinline__ static void step(float* x, float*, const float* u, const StepConsts& c) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float p = x[i], v = x[2 + i], a = u[i];
+            x[i] = p + v * c.dt + a * c.hdt2;
+            x[2 + i] = fminf(fmaxf(v + a * c.dt, -c.vmax), c.vmax);
+        }
+    }
+};
+
+template <>
+struct Dyn<HOLO3D> {
+    static constexpr int DX = 6, DU = 3, DP = 3, AUX = 1;
+    __device__ __forceinline__ static void init(const float*, float*) {}
+    __device__ __forceinline__ static void step(float* x, float*, const float* u, const StepConsts& c) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float p = x[i], v = x[3 + i], a = u[i];
+            x[i] = p + v * c.dt + a * c.hdt2;
+            x[3 + i] = fminf(fmaxf(v + a * c.dt, -c.vmax), c.vmax);
+        }
+    }
+};
+
+template <>
+struct Dyn<UNICYCLE> {
+    static constexpr int DX = 3, DU = 2, DP = 2, AUX = 2;
+    // aux = (cos theta, sin theta) of the current heading
+    __device__ __forceinline__ static void init(const float* x, float* aux) {
+        __sincosf(x[2], &aux[1], &aux[0]);
+    }
+    __device__ __forceinline__ static void step(float* x, float* aux, const float* u,
+                                                const StepConsts& c) {
+        const float v = u[0], om = u[1];
+        const float th_h = x[2] + om * c.hdt;
+        const float th_1 = x[2] + om * c.dt;
+        float sh, ch, s1, c1;
+        __sincosf(th_h, &sh, &ch);
+        __sincosf(th_1, &s1, &c1);
+        const float kv = v * c.dt6;
+        x[0] = x[0] + kv * (aux[0] + 4.0f * ch + c1);
+        x[1] = x[1] + kv * (aux[1] + 4.0f * sh + s1);
+        x[2] = th_1;
+        aux[0] = c1;
+        aux[1] = s1;
+    }
+};
+
+// Squared pair distance in the fixed FP32 order ((dx*dx + dy*dy) + dz*dz).
+template <int DP>
+__device__ __forceinline__ float pair_d2(const float* a, const float* b) {
+#pragma clang fp contract(off)
+    const float d0 = a[0] - b[0];
+    float acc = d0 * d0;
+#pragma unroll
+    for (int c = 1; c < DP; ++c) {
+        const float dc = a[c] - b[c];
+        acc = acc + dc * dc;
+    }
+    return acc;
+}
+
+}  // namespace d4

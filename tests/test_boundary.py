@@ -1,0 +1,81 @@
+"""The C-ABI library without a GPU: it loads, exports every declared symbol,
+its structs match the Python mirror, and bad arguments fail before any launch."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "d4.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int32_t|const char\*)\s+(d4\w*)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2503_12204_amd import _lib
+    return _lib
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L.lib(), n), n
+
+
+def test_struct_layout_matches_header(L, tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "d4.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(d4_problem), offsetof(d4_problem, u_lo),
+         offsetof(d4_problem, flags), offsetof(d4_problem, seed), sizeof(d4_stats),
+         offsetof(d4_stats, status));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    P, S = L.D4Problem, L.D4Stats
+    assert got == [ctypes.sizeof(P), P.u_lo.offset, P.flags.offset, P.seed.offset, ctypes.sizeof(S), S.status.offset]
+
+
+def _bad(L, **kw):
+    from paper_2503_12204_amd import workloads as W
+    p, _, _ = W.holo2d_circle()
+    return L.to_c(p.replace(**kw))
+
+
+@pytest.mark.parametrize("kw", [dict(n_robots=0), dict(n_robots=33), dict(horizon=0), dict(n_samples=0),
+                                dict(n_steps=0), dict(n_steps=70000), dict(dt=0.0), dict(temperature=-1.0),
+                                dict(dyn=7), dict(beta_min=0.0), dict(beta_max=1.0), dict(d0_floor=0.0),
+                                dict(u_lo=(1.0, 1.0, 1.0), u_hi=(-1.0, -1.0, -1.0)), dict(robot_radius=-0.1)])
+def test_invalid_problem_rejected_without_launch(L, kw):
+    c = _bad(L, **kw)
+    buf = (ctypes.c_float * 4)()
+    rc = L.lib().d4_noise(ctypes.byref(c), 0, 1, ctypes.cast(buf, ctypes.c_void_p), None)
+    assert rc == L.D4_EINVAL
+    assert L.lib().d4_last_error().decode()
+
+
+def test_null_and_misaligned_pointers_rejected(L):
+    from paper_2503_12204_amd import workloads as W
+    p, _, _ = W.holo2d_circle()
+    c = L.to_c(p)
+    assert L.lib().d4_noise(ctypes.byref(c), 0, 1, None, None) == L.D4_EINVAL
+    buf = (ctypes.c_float * 8)()
+    odd = ctypes.c_void_p(ctypes.addressof(buf) + 2)
+    assert L.lib().d4_noise(ctypes.byref(c), 0, 1, odd, None) == L.D4_EINVAL
+    assert L.lib().d4_noise(ctypes.byref(c), 0, 0, ctypes.cast(buf, ctypes.c_void_p), None) == L.D4_EINVAL
+    assert L.lib().d4_noise(ctypes.byref(c), 70000, 1, ctypes.cast(buf, ctypes.c_void_p), None) == L.D4_EINVAL
+    assert L.lib().d4_denoise_iter(None, ctypes.byref(c), None, None, None, 0, None, None, None) == L.D4_EINVAL
+    assert L.lib().d4_ctx_create(ctypes.byref(c), None) == L.D4_EINVAL

@@ -106,3 +106,9 @@ def test_streams_differ():
 def test_rejects_wide_counters():
     with pytest.raises(ValueError):
         noise.draw(0, 0, 65536, 1, 4, 4)
+
+
+def test_sample_subset_matches_full_draw():
+    full = noise.draw(5, 1, 0, 3, 40, 13)
+    sub = noise.draw(5, 1, 0, 3, 40, 13, samples=[0, 7, 39, 12])
+    assert np.array_equal(sub, full[:, [0, 7, 39, 12]])
