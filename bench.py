@@ -1,0 +1,198 @@
+"""Benchmark of the denoising hot path on one MI355X.
+
+A step is one deformation iteration (Algorithm 2 loop body): N = 100
+denoising steps of Algorithm 1 (sampling, rollout, reward, softmax weights,
+weighted update) plus the final apply-and-rollout, on the 16-robot 3D
+holonomic sphere swap with T = 100 and M = 8192 samples.  The metric is
+robot*step*samples per second: n * T * M * N per iteration over the measured
+wall time of the iteration, inputs resident in device memory.
+
+The JSON line also carries:
+  roofline      the fused sample+rollout+reward kernel (the dominant kernel):
+                algorithmic VALU operations per launch over its average
+                launch time, measured with HIP events on its stream, against
+                the VALU issue peak of 256 CUs x 64 lanes x 2.4 GHz.
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+VALU_PEAK = 256 * 4 * 16 * 2.4e9      # lane-operations per second
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic VALU operations per robot*step*sample of the fused kernel.
+# Per standard normal: Philox4x32-10 is 10 rounds of two 32x32->64 products
+# (4 ops), four XORs and two key additions = 100 ops per 4 normals (25 each);
+# Box-Muller per pair: uniform (4), ln (30), sqrt and scale (2), sin/cos with
+# quadrant rotation (36), two products (2) = 74 per pair, 37 per normal;
+# 62 ops per normal in all.  Per control component: base + mean, sample, clamp
+# = 4.  Dynamics per step: double integrator 5 per axis; unicycle 13 (two
+# heading updates, two sin/cos pairs, Simpson sums).  Goal term 2 d_p + 3.
+# Pair check 2 d_p + 3 per pair, (n - 1)/2 pairs per robot-step.  Mask 4.
+OPS_PER_NORMAL = 62
+
+
+def ops_per_unit(dyn, n):
+    from paper_2503_12204_amd import workloads as W
+    dx, du, dp = W.dims(dyn)
+    dyn_ops = 13 if dyn == W.UNICYCLE else 5 * dp
+    return du * OPS_PER_NORMAL + 4 * du + dyn_ops + (2 * dp + 3) + (n - 1) / 2.0 * (2 * dp + 3) + 4
+
+
+WORKLOADS = {
+    "holo3d_sphere_swap": "16 robots, 3D holonomic double integrator, antipodal sphere swap, T=100, M=8192, N=100",
+    "unicycle_random": "8 unicycles, random starts/goals in a 10 m box, T=100, M=2048, N=100",
+    "holo2d_circle_swap": "4 robots, 2D holonomic double integrator, antipodal circle swap, T=50, M=256, N=100",
+}
+
+
+def make_workload(name):
+    from paper_2503_12204_amd import workloads as W
+    if name == "holo3d_sphere_swap":
+        return W.holo3d_sphere()
+    if name == "unicycle_random":
+        return W.unicycle_random()
+    if name == "holo2d_circle_swap":
+        return W.holo2d_circle()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(name, target_s=10.0):
+    """The oracle, untouched, on a bounded sample: sampling, rollout, reward
+    and the weighted update of one denoising step for the first S samples,
+    repeated over consecutive steps until about target_s seconds of CPU work."""
+    from oracle import mbd as ombd
+    from oracle import schedule as osched
+    p, x0, g = make_workload(name)
+    S = min(p.n_samples, 1024)
+    sched = osched.step_scalars(p.n_steps, p.beta_min, p.beta_max)
+    ms, sg, os_ = sched
+    du = np.zeros(p.D)
+    ub = np.zeros(p.D)
+    t0 = time.perf_counter()
+    steps = 0
+    i = p.n_steps
+    while True:
+        out = ombd.sample_rewards(p, x0, g, ub, du, 0, i, sched=sched, samples=np.arange(S))
+        du, _ = ombd.mc_update(du, out["eps"], out["r"], ms[i], sg[i], os_[i], p.temperature, True)
+        steps += 1
+        i -= 1
+        if time.perf_counter() - t0 >= target_s or i == 0:
+            break
+    dt = time.perf_counter() - t0
+    units = p.n_robots * p.horizon * S * steps
+    return {"value": units / dt, "unit": "robot*step*samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} denoising steps of {name} restricted to samples 0..{S - 1} "
+                      f"(sampling, FP64 rollout, reward, weighted update), {dt:.1f} s, single-threaded NumPy"}
+
+
+def time_fused_kernel(L, p, x0, g, reps=30):
+    """Average duration of the fused sample+rollout+reward kernel, bracketed by
+    HIP events on the stream it is launched on (torch's current stream)."""
+    import torch
+    D, M = p.D, p.n_samples
+    eps = torch.empty((D, M), dtype=torch.float32, device="cuda")
+    r = torch.empty(M, dtype=torch.float32, device="cuda")
+    hits = torch.empty(M, dtype=torch.int32, device="cuda")
+    ub = torch.zeros(D, dtype=torch.float32, device="cuda")
+    du = torch.zeros(D, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        L.sample_rollout_fitness(p, x0, g, ub, du, 0, 100, eps, r, hits)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for k in range(reps):
+        L.sample_rollout_fitness(p, x0, g, ub, du, 0, 100 - (k % 100), eps, r, hits)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="holo3d_sphere_swap", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--kernel-only", type=int, default=0,
+                    help="only launch the fused kernel this many times (for counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the planner's hot path runs on a single device "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_12204_amd import _lib as L
+    from paper_2503_12204_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    p, x0n, gn = make_workload(args.workload)
+    x0 = torch.as_tensor(x0n, device="cuda")
+    g = torch.as_tensor(gn, device="cuda")
+
+    if args.kernel_only:
+        print(f"fused kernel x{args.kernel_only} on {args.workload}", flush=True)
+        time_fused_kernel(L, p, x0, g, reps=args.kernel_only)
+        n_bytes = 256 << 20
+        a = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("copy calibration: 256 MiB read + 256 MiB write", flush=True)
+        return
+
+    u = torch.zeros((p.n_robots, p.horizon, p.du), dtype=torch.float32, device="cuda")
+    ctx = L.Context(p)
+    for k in range(args.warmup):
+        ctx.denoise_iter(x0, g, u, k, sync=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ctx.denoise_iter(x0, g, u, args.warmup + k, sync=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = ctx.denoise_iter(x0, g, u, args.warmup + args.steps)
+    ctx.close()
+    ms_per_step = elapsed / args.steps * 1e3
+    units = p.n_robots * p.horizon * p.n_samples * p.n_steps
+    value = units / (elapsed / args.steps)
+
+    t_k = time_fused_kernel(L, p, x0, g)
+    ops = ops_per_unit(p.dyn, p.n_robots) * p.n_robots * p.horizon * p.n_samples
+    achieved = ops / t_k
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "kernel": "k_rollfit (fused sample+rollout+reward)", "kernel_us": t_k * 1e6,
+                "ops_per_unit": ops_per_unit(p.dyn, p.n_robots)}
+    out = {
+        "metric": "robot*step*samples/s in rollout+fitness (whole denoising iteration)",
+        "value": value, "unit": "robot*step*samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "robots": p.n_robots, "horizon": p.horizon, "samples": p.n_samples,
+                   "denoising_steps": p.n_steps, "dynamics": W.DYN_NAMES[p.dyn]},
+        "roofline": roofline,
+        "last_iteration": {"reward": st["reward"], "hits": st["hits"], "success": st["success"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
