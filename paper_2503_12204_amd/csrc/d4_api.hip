@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -145,17 +146,23 @@ struct Tile {
     int S, Tb;
 };
 
-// Samples per workgroup and time-block length of the reward kernels.
+// Samples per workgroup and time-block length of the reward kernels: 16
+// samples per workgroup (fewer when n*S would pass 1024 lanes), and a time
+// block sized so that the double-buffered positions stay near 32 KiB.
 Tile pick_tile(const d4_problem* p) {
     const int n = p->n_robots;
-    int S = 64;
-    while (S > 1 && S * n > 256) S >>= 1;
+    int S = 16;
+    while (S > 1 && S * n > 1024) S >>= 1;
+    const int slot = shape_of(p->dyn).dp == 3 ? 16 : 8;
+    const int per_step = 2 * n * S * slot;
+    int Tb = (32 * 1024) / per_step;
+    const int cs = shape_of(p->dyn).du == 2 ? 2 : 4;
+    Tb = std::max(cs, std::min(16, Tb / cs * cs));
     const char* env = std::getenv("D4_TILE_S");
     if (env) {
         int v = std::atoi(env);
-        if (v >= 1 && v * n <= 1024) S = v;
+        if (v >= 1 && v <= 64 && v * n <= 1024) S = v;
     }
-    int Tb = 4;
     const char* envt = std::getenv("D4_TILE_TB");
     if (envt) {
         int v = std::atoi(envt);
@@ -167,9 +174,18 @@ Tile pick_tile(const d4_problem* p) {
 size_t rollfit_lds(const d4_problem* p, Tile t) {
     const Shape s = shape_of(p->dyn);
     const size_t n = p->n_robots;
-    const size_t a = (size_t)2 * t.Tb * s.dp * n * t.S + (size_t)2 * t.Tb * t.S;
-    const size_t b = (size_t)3 * n * t.S;
-    return 4 * (a > b ? a : b);
+    const size_t slot = s.dp == 3 ? 16 : 8;
+    const size_t a = (size_t)2 * t.Tb * n * t.S * slot + (size_t)2 * t.Tb * t.S * 4;
+    const size_t b = (size_t)3 * n * t.S * 4;
+    return a > b ? a : b;
+}
+
+// Steps per noise chunk of the aligned fused kernel (whole Philox blocks).
+int chunk_steps(int du) { return du == 2 ? 2 : 4; }
+
+bool aligned_ok(const d4_problem* p, Tile t) {
+    const int du = shape_of(p->dyn).du;
+    return ((p->horizon * du) % 4 == 0) && (t.Tb % chunk_steps(du) == 0) && !std::getenv("D4_NO_ALIGNED");
 }
 
 RollFitArgs base_args(const d4_problem* p, Tile tile) {
@@ -195,52 +211,79 @@ RollFitArgs base_args(const d4_problem* p, Tile tile) {
     return a;
 }
 
+// Dynamic LDS above 64 KiB must be enabled per kernel (gfx950: 160 KiB per CU).
+template <typename K>
+void allow_lds(K kernel, size_t lds) {
+    if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int DYN>
+void launch_rollfit_dyn(int mode, dim3 grid, dim3 block, size_t lds, hipStream_t st, const RollFitArgs& a) {
+    if (mode == MODE_ALIGNED) {
+        allow_lds(k_rollfit<DYN, MODE_ALIGNED>, lds);
+        hipLaunchKernelGGL((k_rollfit<DYN, MODE_ALIGNED>), grid, block, lds, st, a);
+    } else if (mode == MODE_STREAM) {
+        allow_lds(k_rollfit<DYN, MODE_STREAM>, lds);
+        hipLaunchKernelGGL((k_rollfit<DYN, MODE_STREAM>), grid, block, lds, st, a);
+    } else {
+        allow_lds(k_rollfit<DYN, MODE_FROM_X>, lds);
+        hipLaunchKernelGGL((k_rollfit<DYN, MODE_FROM_X>), grid, block, lds, st, a);
+    }
+}
+
 template <bool FROM_X>
 int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStream_t st) {
     const dim3 grid((p->n_samples + tile.S - 1) / tile.S);
     const dim3 block(tile.S * p->n_robots);
     const size_t lds = rollfit_lds(p, tile);
-    if (lds > 65536) return fail(D4_EUNSUPPORTED, "reward kernel needs %zu bytes of LDS", lds);
+    if (lds > 160 * 1024) return fail(D4_EUNSUPPORTED, "reward kernel needs %zu bytes of LDS", lds);
+    const int mode = FROM_X ? MODE_FROM_X : (aligned_ok(p, tile) ? MODE_ALIGNED : MODE_STREAM);
     switch (p->dyn) {
-        case HOLO2D: hipLaunchKernelGGL((k_rollfit<HOLO2D, FROM_X>), grid, block, lds, st, a); break;
-        case HOLO3D: hipLaunchKernelGGL((k_rollfit<HOLO3D, FROM_X>), grid, block, lds, st, a); break;
-        default: hipLaunchKernelGGL((k_rollfit<UNICYCLE, FROM_X>), grid, block, lds, st, a); break;
+        case HOLO2D: launch_rollfit_dyn<HOLO2D>(mode, grid, block, lds, st, a); break;
+        case HOLO3D: launch_rollfit_dyn<HOLO3D>(mode, grid, block, lds, st, a); break;
+        default: launch_rollfit_dyn<UNICYCLE>(mode, grid, block, lds, st, a); break;
     }
     HIP_LAUNCH_CHECK("k_rollfit");
     return D4_OK;
 }
 
-int launch_softmax(const d4_problem* p, const float* r, float* w, int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_softmax, dim3(1), dim3(1024), 0, st, r, w, p->n_samples,
-                       1.0f / p->temperature, (int)(p->flags & FLAG_NORMALIZE), status);
-    HIP_LAUNCH_CHECK("k_softmax");
-    return D4_OK;
-}
-
-int launch_reduce(const d4_problem* p, const float* eps, const float* w, const float* du_in,
-                  float* du_out, float ms, float sigma, float os, hipStream_t st) {
+// Weighted update of step i: softmax weights from the reward statistics, the
+// weighted sum of the draws and the rescaled deformation.
+int launch_update(const d4_problem* p, const float* eps, const float* r, const float4* partials, int P,
+                  const float* du_in, float* du_out, float* w_out, int* status, float ms, float sigma,
+                  float os, hipStream_t st) {
     const int D = p->n_robots * p->horizon * shape_of(p->dyn).du;
     const int M = p->n_samples;
-    const bool vec = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(eps) & 15u) == 0) &&
-                     ((reinterpret_cast<uintptr_t>(w) & 15u) == 0);
-    const bool staged = M <= 16384;
+    if (M > 16384) return fail(D4_EUNSUPPORTED, "n_samples %d above the 16384 weights one workgroup stages", M);
+    UpdateArgs a;
+    a.eps = eps;
+    a.r = r;
+    a.partials = partials;
+    a.du_in = du_in;
+    a.du_out = du_out;
+    a.w_out = w_out;
+    a.status = status;
+    a.D = D;
+    a.M = M;
+    a.P = P;
+    a.inv_lam = 1.0f / p->temperature;
+    a.normalize = (p->flags & FLAG_NORMALIZE) ? 1 : 0;
+    a.ms = ms;
+    a.sigma = sigma;
+    a.os = os;
+    const bool vec = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(eps) & 15u) == 0);
     const int waves = 4;
     int grid = (D + waves - 1) / waves;
-    if (grid > 1024) grid = 1024;
-    const size_t lds = staged ? (size_t)M * 4 : 0;
-    if (staged && vec)
-        hipLaunchKernelGGL((k_reduce_update<true, true>), dim3(grid), dim3(64 * waves), lds, st, eps, w,
-                           du_in, du_out, D, M, ms, sigma, os);
-    else if (staged)
-        hipLaunchKernelGGL((k_reduce_update<true, false>), dim3(grid), dim3(64 * waves), lds, st, eps, w,
-                           du_in, du_out, D, M, ms, sigma, os);
-    else if (vec)
-        hipLaunchKernelGGL((k_reduce_update<false, true>), dim3(grid), dim3(64 * waves), 0, st, eps, w,
-                           du_in, du_out, D, M, ms, sigma, os);
+    int cap = 1024;
+    if (const char* e = std::getenv("D4_UPD_GRID")) cap = std::max(1, std::atoi(e));
+    if (grid > cap) grid = cap;
+    const size_t lds = (size_t)M * 4;
+    if (vec)
+        hipLaunchKernelGGL((k_softmax_update<true>), dim3(grid), dim3(64 * waves), lds, st, a);
     else
-        hipLaunchKernelGGL((k_reduce_update<false, false>), dim3(grid), dim3(64 * waves), 0, st, eps, w,
-                           du_in, du_out, D, M, ms, sigma, os);
-    HIP_LAUNCH_CHECK("k_reduce_update");
+        hipLaunchKernelGGL((k_softmax_update<false>), dim3(grid), dim3(64 * waves), lds, st, a);
+    HIP_LAUNCH_CHECK("k_softmax_update");
     return D4_OK;
 }
 
@@ -255,6 +298,7 @@ struct d4_ctx {
     hipGraph_t graph;
     hipGraphExec_t exec;
     float *eps, *r, *w, *du_a, *du_b, *x0, *goal, *ubase, *traj, *stats;
+    float4* partials;
     int* hits;
     int* status;
     uint32_t* iter;
@@ -266,6 +310,7 @@ void free_ctx_buffers(d4_ctx* c) {
     float* fb[] = {c->eps, c->r, c->w, c->du_a, c->du_b, c->x0, c->goal, c->ubase, c->traj, c->stats};
     for (float* f : fb)
         if (f) (void)hipFree(f);
+    if (c->partials) (void)hipFree(c->partials);
     if (c->hits) (void)hipFree(c->hits);
     if (c->status) (void)hipFree(c->status);
     if (c->iter) (void)hipFree(c->iter);
@@ -299,7 +344,9 @@ int enqueue_iteration(d4_ctx* c, hipStream_t st) {
     a.r = c->r;
     a.hits = c->hits;
     a.robots_hit = nullptr;
+    a.partials = c->partials;
     a.iter_dev = c->iter;
+    const int P = (p->n_samples + tile.S - 1) / tile.S;
     for (int i = p->n_steps; i >= 1; --i) {
         a.du_in = du_cur;
         a.step = (uint32_t)i;
@@ -307,9 +354,8 @@ int enqueue_iteration(d4_ctx* c, hipStream_t st) {
         a.sigma = sc.sigma[i];
         int rc = launch_rollfit<false>(p, a, tile, st);
         if (rc) return rc;
-        rc = launch_softmax(p, c->r, c->w, c->status, st);
-        if (rc) return rc;
-        rc = launch_reduce(p, c->eps, c->w, du_cur, du_nxt, sc.ms[i], sc.sigma[i], sc.os[i], st);
+        rc = launch_update(p, c->eps, c->r, c->partials, P, du_cur, du_nxt, nullptr, c->status, sc.ms[i],
+                           sc.sigma[i], sc.os[i], st);
         if (rc) return rc;
         float* t = du_cur;
         du_cur = du_nxt;
@@ -460,16 +506,25 @@ int32_t d4_score_update(const d4_problem* p, const float* r, const float* eps, c
     if (step < 1 || step > p->n_steps) return fail(D4_EINVAL, "step %d outside 1..N", step);
     if (du_out == du_in) return fail(D4_EINVAL, "du_out must not alias du_in");
     hipStream_t st = (hipStream_t)stream;
-    float* w = w_out;
-    if (w) NEED(w);
-    if (!w) {
-        // weights are needed by the reduction; use a transient buffer
-        HIP_TRY(hipMallocAsync((void**)&w, sizeof(float) * (size_t)p->n_samples, st));
+    if (w_out) NEED(w_out);
+    if (p->n_samples > 16384)
+        return fail(D4_EUNSUPPORTED, "n_samples %d above the 16384 weights one workgroup stages", p->n_samples);
+    // chunk the rewards as the fused kernel's workgroups do, so that a split
+    // sequence of calls reproduces d4_denoise_iter bit for bit
+    const int S = pick_tile(p).S;
+    const int P = (p->n_samples + S - 1) / S;
+    float4* partials = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&partials, sizeof(float4) * (size_t)P, st));
+    hipLaunchKernelGGL(k_reward_partials, dim3(P), dim3(64), 0, st, r, p->n_samples, S, partials);
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) {
+        (void)hipFreeAsync(partials, st);
+        return fail(D4_EHIP, "launch of k_reward_partials failed: %s", hipGetErrorString(le));
     }
     const Schedule sc = make_schedule(p);
-    rc = launch_softmax(p, r, w, nullptr, st);
-    if (!rc) rc = launch_reduce(p, eps, w, du_in, du_out, sc.ms[step], sc.sigma[step], sc.os[step], st);
-    if (!w_out) (void)hipFreeAsync(w, st);
+    rc = launch_update(p, eps, r, partials, P, du_in, du_out, w_out, nullptr, sc.ms[step], sc.sigma[step],
+                       sc.os[step], st);
+    (void)hipFreeAsync(partials, st);
     return rc;
 }
 
@@ -477,6 +532,8 @@ int32_t d4_ctx_create(const d4_problem* p, d4_ctx** out) {
     int rc = validate(p);
     if (rc) return rc;
     if (!out) return fail(D4_EINVAL, "ctx out-pointer is NULL");
+    if (p->n_samples > 16384)
+        return fail(D4_EUNSUPPORTED, "n_samples %d above the 16384 weights one workgroup stages", p->n_samples);
     d4_ctx* c = new (std::nothrow) d4_ctx;
     if (!c) return fail(D4_ENOMEM, "host allocation failed");
     std::memset(c, 0, sizeof *c);
@@ -494,6 +551,7 @@ int32_t d4_ctx_create(const d4_problem* p, d4_ctx** out) {
         {(void**)&c->goal, 4 * n * s.dp}, {(void**)&c->ubase, 4 * D}, {(void**)&c->traj, 4 * n * (T + 1) * s.dx},
         {(void**)&c->stats, sizeof(d4_stats)}, {(void**)&c->hits, 4 * M}, {(void**)&c->status, 4},
         {(void**)&c->iter, 4},
+        {(void**)&c->partials, sizeof(float4) * (M + 1)},
     };
     for (auto& a : allocs) {
         if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {

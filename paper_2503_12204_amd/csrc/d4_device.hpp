@@ -31,10 +31,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -57,10 +57,9 @@ __device__ __forceinline__ float ln_unit(float u) {
     const uint32_t b = __float_as_uint(u);
     int e = (int)(b >> 23) - 127;
     float f = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
-    if (f >= 1.5f) {
-        f = f * 0.5f;
-        e += 1;
-    }
+    const bool big = f >= 1.5f;
+    f = big ? f * 0.5f : f;
+    e += big ? 1 : 0;
     const float s = (f - 1.0f) / (f + 1.0f);
     const float s2 = s * s;
     float q = A11 * s2 + A9;
@@ -101,9 +100,13 @@ __device__ __forceinline__ void sincos_2pi_word(uint32_t word, float& sn_o, floa
     cp = cp * y2 + C4;
     cp = cp * y2 + C2;
     const float cs = 1.0f + y2 * cp;
-    const int qq = q & 3;
-    sn_o = qq == 0 ? sn : qq == 1 ? cs : qq == 2 ? -sn : -cs;
-    cs_o = qq == 0 ? cs : qq == 1 ? -sn : qq == 2 ? -cs : sn;
+    // rotate by q quarter turns: swap on odd q, then exact sign flips
+    // (sin: q = 2, 3; cos: q = 1, 2)
+    const uint32_t qq = (uint32_t)q & 3u;
+    const float a = (qq & 1u) ? cs : sn;
+    const float b = (qq & 1u) ? sn : cs;
+    sn_o = __uint_as_float(__float_as_uint(a) ^ ((qq & 2u) << 30));
+    cs_o = __uint_as_float(__float_as_uint(b) ^ (((qq + 1u) & 2u) << 30));
 }
 
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z_even, float& z_odd) {
@@ -153,6 +156,10 @@ struct NormalStream {
         return j == 0 ? z0 : j == 1 ? z1 : j == 2 ? z2 : z3;
     }
 };
+
+// Square root outside the bit-exact recipe (goal distances): one hardware
+// v_sqrt_f32 (1 ulp) instead of the correctly rounded sequence.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // ---------------------------------------------------------------- dynamics
 struct StepConsts {

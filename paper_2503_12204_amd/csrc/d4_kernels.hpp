@@ -2,18 +2,20 @@
 //
 //  k_noise             - standard normal draws eps[e][m] (sampling step of Algorithm 1)
 //  k_rollout           - RK4 rollout of given controls (Section III, Section IV-C)
-//  k_rollfit<DYN,X>    - reward of trajectories (Eq. generic-reward): with X = false the
-//                        fused sample + rollout + reward of one denoising step, with X = true
-//                        the reward of trajectories read from memory
-//  k_softmax           - batch normalisation and softmax weights (p_0 of Section IV-B)
-//  k_reduce_update     - S[e] = sum_m w_m eps[e][m] and the one-step update (Eq. mbd-denoising)
+//  k_rollfit<DYN,MODE> - reward of trajectories (Eq. generic-reward): the fused sample +
+//                        rollout + reward of one denoising step (draws streamed per element,
+//                        or generated in whole Philox blocks when aligned), or the reward of
+//                        trajectories read from memory
+//  k_softmax_update    - batch normalisation, softmax weights (p_0 of Section IV-B),
+//                        S[e] = sum_m w_m eps[e][m] and the one-step update (Eq. mbd-denoising)
+//  k_reward_partials   - per-chunk reward statistics feeding k_softmax_update
 //  k_apply_final       - tau.u <- clip(tau.u + Delta U_0), rollout and stats (Algorithm 2)
 //
 // Lane mapping of k_rollfit: one lane per (sample m, robot k) with the sample
 // index fastest, S samples per workgroup (blockDim = n*S).  A lane keeps its
 // robot's state in registers and walks t = 0..T-1; positions of a block of Tb
-// steps go to LDS as [Tb][d_p][n][S] so that the pair checks of one step read
-// consecutive addresses across a wave.  Lane k checks partners (k + j) mod n
+// steps go to LDS as [Tb][n][S] float2/float4 slots so that the pair checks of
+// one step read consecutive slots across a wave.  Lane k checks partners (k + j) mod n
 // for j = 1..floor((n-1)/2), plus j = n/2 for k < n/2 when n is even: every
 // unordered pair exactly once, spread evenly.  The per-(m, t) "robot k hit
 // anything" bits are OR-ed into an LDS word; positions and masks are double
@@ -23,6 +25,18 @@
 #include "d4_device.hpp"
 
 namespace d4 {
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
 
 struct RollFitArgs {
     const float* x0;      // [n][dx]
@@ -34,6 +48,7 @@ struct RollFitArgs {
     float* r;             // [M]
     int* hits;            // [M]
     int* robots_hit;      // [M] or null
+    float4* partials;     // [gridDim] reward statistics of each workgroup, or null
     const uint32_t* iter_dev;  // iteration index in device memory, or null
     int n, T, M, S, Tb;
     float mean_scale, sigma;
@@ -44,10 +59,48 @@ struct RollFitArgs {
     uint32_t flags;
 };
 
-template <int DYN, bool FROM_X>
+// Position slot of one robot in LDS: float2 in the plane, float4 (w unused) in space.
+template <int DP>
+struct PosSlot;
+template <>
+struct PosSlot<2> {
+    using T = float2;
+    __device__ __forceinline__ static T pack(const float* x) { return make_float2(x[0], x[1]); }
+    __device__ __forceinline__ static void unpack(const T& v, float* p) {
+        p[0] = v.x;
+        p[1] = v.y;
+    }
+};
+template <>
+struct PosSlot<3> {
+    using T = float4;
+    __device__ __forceinline__ static T pack(const float* x) { return make_float4(x[0], x[1], x[2], 0.0f); }
+    __device__ __forceinline__ static void unpack(const T& v, float* p) {
+        p[0] = v.x;
+        p[1] = v.y;
+        p[2] = v.z;
+    }
+};
+
+enum { MODE_STREAM = 0, MODE_ALIGNED = 1, MODE_FROM_X = 2 };
+
+// Steps per noise chunk (a whole number of Philox blocks) and blocks per chunk.
+template <int DU>
+struct Chunk {
+    static constexpr int STEPS = (DU == 2) ? 2 : 4;
+    static constexpr int GROUPS = STEPS * DU / 4;
+};
+
+// Reward of one (sample, robot) lane per step block; see the mapping notes above.
+// MODE_ALIGNED requires T * d_u % 4 == 0 and Tb a multiple of Chunk::STEPS so
+// that every chunk of a robot's elements starts on a Philox block boundary.
+template <int DYN, int MODE>
 __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
     using DY = Dyn<DYN>;
     constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
+    using PS = PosSlot<DP>;
+    using PT = typename PS::T;
+    constexpr bool FROM_X = MODE == MODE_FROM_X;
     extern __shared__ float lds[];
     const int n = a.n, T = a.T, M = a.M, S = a.S, Tb = a.Tb;
     const int tid = threadIdx.x;
@@ -56,8 +109,8 @@ __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
     const int m = blockIdx.x * S + ms;
     const bool live = m < M;
     const int mc = live ? m : M - 1;
-    float* pos = lds;                                                   // [2][Tb][DP][n][S]
-    uint32_t* mask = reinterpret_cast<uint32_t*>(lds + 2 * Tb * DP * n * S);  // [2][Tb][S]
+    PT* pos = reinterpret_cast<PT*>(lds);                                        // [2][Tb][n][S]
+    uint32_t* mask = reinterpret_cast<uint32_t*>(pos + 2 * Tb * n * S);          // [2][Tb][S]
 
     float x[DX], aux[DY::AUX], g[DP];
     if (FROM_X) {
@@ -74,76 +127,114 @@ __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
     float d0s = 0.0f;
 #pragma unroll
     for (int c = 0; c < DP; ++c) d0s += (x[c] - g[c]) * (x[c] - g[c]);
-    const float inv_d0 = 1.0f / fmaxf(sqrtf(d0s), a.d0_floor);
+    const float inv_d0 = 1.0f / fmaxf(fast_sqrt(d0s), a.d0_floor);
 
     float goal_acc = 0.0f;
     int safe_cnt = 0, hit_cnt = 0;
 
-    NormalStream ns;
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
-    ns.init((uint32_t)mc, (iter << 16) | a.step, a.inst, a.key0, a.key1);
+    const uint32_t c2 = (iter << 16) | a.step;
+    NormalStream ns;
+    ns.init((uint32_t)mc, c2, a.inst, a.key0, a.key1);
     float ulo[DU], uhi[DU];
 #pragma unroll
     for (int d = 0; d < DU; ++d) {
         ulo[d] = a.ulo[d];
         uhi[d] = a.uhi[d];
     }
-    const int jhalf = (n - 1) >> 1;
-    const bool extra = ((n & 1) == 0) && (k < (n >> 1));
+    const float sigma = a.sigma, mscale = a.mean_scale;
+    const int jmax = ((n - 1) >> 1) + ((((n & 1) == 0) && (k < (n >> 1))) ? 1 : 0);
     const bool pairs_mode = (a.flags & FLAG_SAFE_PAIRS) != 0;
+    const size_t Ms = (size_t)M;
+
+    // goal term and LDS position of the state after step t (slot tt of buffer buf)
+    auto after_step = [&](int buf, int tt) {
+        float dist2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < DP; ++c) dist2 += (x[c] - g[c]) * (x[c] - g[c]);
+        goal_acc += 1.0f - fast_sqrt(dist2) * inv_d0;
+        pos[((buf * Tb + tt) * n + k) * S + ms] = PS::pack(x);
+    };
 
     const int nblk = (T + Tb - 1) / Tb;
     for (int b = 0; b < nblk; ++b) {
         const int buf = b & 1;
         const int t0 = b * Tb;
         const int tcount = min(Tb, T - t0);
-        for (int tt = 0; tt < tcount; ++tt) {
-            const int t = t0 + tt;
-            if (FROM_X) {
-                const float* xr = a.xs + (((size_t)mc * n + k) * (size_t)(T + 1) + (t + 1)) * DX;
-#pragma unroll
-                for (int c = 0; c < DP; ++c) x[c] = xr[c];
-            } else {
-                float u[DU];
+        if (MODE == MODE_ALIGNED) {
+            constexpr int CS = Chunk<DU>::STEPS, CG = Chunk<DU>::GROUPS;
+            for (int tc = 0; tc < tcount; tc += CS) {
+                const int t = t0 + tc;
                 const uint32_t e0 = (uint32_t)((k * T + t) * DU);
+                float z[4 * CG];
 #pragma unroll
-                for (int d = 0; d < DU; ++d) {
-                    const uint32_t e = e0 + d;
-                    const float z = ns.get(e);
-                    if (live) a.eps[(size_t)e * M + m] = z;
-                    const float cb = a.u_base[e] + a.du_in[e] * a.mean_scale;
-                    u[d] = fminf(fmaxf(cb + a.sigma * z, ulo[d]), uhi[d]);
+                for (int q = 0; q < CG; ++q)
+                    normal_block((e0 >> 2) + q, (uint32_t)mc, c2, a.inst, a.key0, a.key1, z[4 * q],
+                                 z[4 * q + 1], z[4 * q + 2], z[4 * q + 3]);
+                if (live) {
+#pragma unroll
+                    for (int j = 0; j < 4 * CG; ++j) a.eps[(size_t)(e0 + j) * Ms + m] = z[j];
                 }
-                DY::step(x, aux, u, a.sc);
+#pragma unroll
+                for (int s = 0; s < CS; ++s) {
+                    float u[DU];
+#pragma unroll
+                    for (int d = 0; d < DU; ++d) {
+                        const uint32_t e = e0 + s * DU + d;
+                        const float cb = a.u_base[e] + a.du_in[e] * mscale;
+                        u[d] = fminf(fmaxf(cb + sigma * z[s * DU + d], ulo[d]), uhi[d]);
+                    }
+                    DY::step(x, aux, u, a.sc);
+                    after_step(buf, tc + s);
+                }
             }
-            float dist2 = 0.0f;
+        } else {
+            for (int tt = 0; tt < tcount; ++tt) {
+                const int t = t0 + tt;
+                if (FROM_X) {
+                    const float* xr = a.xs + (((size_t)mc * n + k) * (size_t)(T + 1) + (t + 1)) * DX;
 #pragma unroll
-            for (int c = 0; c < DP; ++c) dist2 += (x[c] - g[c]) * (x[c] - g[c]);
-            goal_acc += 1.0f - sqrtf(dist2) * inv_d0;
+                    for (int c = 0; c < DP; ++c) x[c] = xr[c];
+                } else {
+                    float u[DU];
+                    const uint32_t e0 = (uint32_t)((k * T + t) * DU);
 #pragma unroll
-            for (int c = 0; c < DP; ++c) pos[(((buf * Tb + tt) * DP + c) * n + k) * S + ms] = x[c];
+                    for (int d = 0; d < DU; ++d) {
+                        const uint32_t e = e0 + d;
+                        const float z = ns.get(e);
+                        if (live) a.eps[(size_t)e * Ms + m] = z;
+                        const float cb = a.u_base[e] + a.du_in[e] * mscale;
+                        u[d] = fminf(fmaxf(cb + sigma * z, ulo[d]), uhi[d]);
+                    }
+                    DY::step(x, aux, u, a.sc);
+                }
+                after_step(buf, tt);
+            }
         }
         if (k == 0)
             for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
         __syncthreads();
         for (int tt = 0; tt < tcount; ++tt) {
-            const float* pb = pos + ((buf * Tb + tt) * DP) * n * S + ms;
+            const PT* pb = pos + (buf * Tb + tt) * n * S + ms;
+            const PT* pend = pb + n * S;
+            const PT* q = pb + k * S;
             float pk[DP];
-#pragma unroll
-            for (int c = 0; c < DP; ++c) pk[c] = pb[(c * n + k) * S];
+            PS::unpack(*q, pk);
             uint32_t bits = 0u;
-            const int jmax = jhalf + (extra ? 1 : 0);
-            for (int j = 1; j <= jmax; ++j) {
-                int l = k + j;
-                if (l >= n) l -= n;
-                float pl[DP];
-#pragma unroll
-                for (int c = 0; c < DP; ++c) pl[c] = pb[(c * n + l) * S];
-                if (pair_d2<DP>(pk, pl) <= a.thr2) {
-                    bits |= 1u << l;
-                    ++hit_cnt;
+            int l = k;
+#pragma unroll 4
+            for (int j = 0; j < jmax; ++j) {
+                q += S;
+                ++l;
+                if (q == pend) {
+                    q = pb;
+                    l = 0;
                 }
+                float pl[DP];
+                PS::unpack(*q, pl);
+                bits |= (pair_d2<DP>(pk, pl) <= a.thr2) ? (1u << l) : 0u;
             }
+            hit_cnt += __popc(bits);
             if (bits) atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));
         }
         __syncthreads();
@@ -167,9 +258,22 @@ __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
             hs += rh[kk * S + ms];
         }
         const float pen = pairs_mode ? (float)(2 * hs) : (float)ss;
-        a.r[m] = (gs - a.w_safe * pen) / (float)(n * T);
+        const float rv = (gs - a.w_safe * pen) / (float)(n * T);
+        a.r[m] = rv;
         a.hits[m] = hs;
         if (a.robots_hit) a.robots_hit[m] = ss;
+        rg[ms] = rv;
+    }
+    if (a.partials && tid < 64) {
+        // statistics of this workgroup's rewards (S <= 64 lanes of wave 0)
+        const bool mine = tid < S && (blockIdx.x * S + tid) < M;
+        const float rv = mine ? rg[tid] : 0.0f;
+        const float cnt = wave_sum(mine ? 1.0f : 0.0f);
+        const float mean = wave_sum(rv) / cnt;
+        const float dv = mine ? rv - mean : 0.0f;
+        const float m2 = wave_sum(dv * dv);
+        const float mx = wave_max(mine ? rv : -INFINITY);
+        if (tid == 0) a.partials[blockIdx.x] = make_float4(cnt, mean, m2, mx);
     }
 }
 
@@ -217,103 +321,122 @@ __global__ void __launch_bounds__(256) k_rollout(const float* x0, const float* u
     }
 }
 
-// ------------------------------------------------------------- reductions
-__device__ __forceinline__ float wave_sum(float v) {
+// Chan's pairwise combination of (count, mean, M2, max) summaries.
+__device__ __forceinline__ float4 chan_combine(float4 a, float4 b) {
+    if (b.x == 0.0f) return a;
+    if (a.x == 0.0f) return b;
+    const float nn = a.x + b.x;
+    const float d = b.y - a.y;
+    const float f = b.x / nn;
+    return make_float4(nn, a.y + d * f, a.z + b.z + d * d * a.x * f, fmaxf(a.w, b.w));
+}
+
+__device__ __forceinline__ float4 wave_combine(float4 v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 32; o > 0; o >>= 1) {
+        float4 u;
+        u.x = __shfl_xor(v.x, o, 64);
+        u.y = __shfl_xor(v.y, o, 64);
+        u.z = __shfl_xor(v.z, o, 64);
+        u.w = __shfl_xor(v.w, o, 64);
+        // combine in a fixed order (lower lane first) so every lane agrees bit for bit
+        v = ((threadIdx.x & o) == 0) ? chan_combine(v, u) : chan_combine(u, v);
+    }
     return v;
 }
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
+
+// Reward statistics of consecutive S-sample chunks (S <= 64), computed exactly
+// as the fused kernel's tail computes them for its workgroups of S samples.
+__global__ void __launch_bounds__(64) k_reward_partials(const float* r, int M, int S, float4* partials) {
+    const int m = blockIdx.x * S + threadIdx.x;
+    const bool mine = (int)threadIdx.x < S && m < M;
+    const float rv = mine ? r[m] : 0.0f;
+    const float cnt = wave_sum(mine ? 1.0f : 0.0f);
+    const float mean = wave_sum(rv) / cnt;
+    const float dv = mine ? rv - mean : 0.0f;
+    const float m2 = wave_sum(dv * dv);
+    const float mx = wave_max(mine ? rv : -INFINITY);
+    if (threadIdx.x == 0) partials[blockIdx.x] = make_float4(cnt, mean, m2, mx);
 }
 
-// Block-wide reduction for blockDim a multiple of 64 (<= 1024); all threads get the result.
-template <bool MAX>
-__device__ __forceinline__ float block_reduce(float v, float* red) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = MAX ? wave_max(v) : wave_sum(v);
-    __syncthreads();
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    float r = red[0];
-    for (int i = 1; i < nw; ++i) r = MAX ? fmaxf(r, red[i]) : r + red[i];
-    return r;
-}
+struct UpdateArgs {
+    const float* eps;        // [D][M]
+    const float* r;          // [M]
+    const float4* partials;  // [P] reward statistics
+    const float* du_in;      // [D]
+    float* du_out;           // [D]
+    float* w_out;            // [M] or null (written by workgroup 0)
+    int* status;             // set to D4_ENONFINITE on a non-finite reward, or null
+    int D, M, P;
+    float inv_lam;
+    int normalize;
+    float ms, sigma, os;
+};
 
-// Softmax weights of one batch of rewards; a non-finite reward sets *status
-// and falls back to uniform weights.
-__global__ void __launch_bounds__(1024) k_softmax(const float* r, float* w, int M, float inv_lam,
-                                                  int normalize, int* status) {
-    __shared__ float red[16];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    float s = 0.0f;
-    int bad = 0;
-    for (int i = tid; i < M; i += nt) {
-        const float v = r[i];
-        bad |= !isfinite(v);
-        s += v;
-    }
-    const float nbad = block_reduce<false>((float)bad, red);
-    if (nbad > 0.0f) {
-        for (int i = tid; i < M; i += nt) w[i] = 1.0f / (float)M;
-        if (tid == 0 && status) *status = -4;
-        return;
-    }
-    float mu = 0.0f, scale = inv_lam;
-    if (normalize) {
-        mu = block_reduce<false>(s, red) / (float)M;
-        float q = 0.0f;
-        for (int i = tid; i < M; i += nt) {
-            const float d = r[i] - mu;
-            q += d * d;
-        }
-        const float var = block_reduce<false>(q, red) / (float)M;
-        scale = inv_lam / fmaxf(sqrtf(var), 1e-6f);
-    }
-    float mx = -INFINITY;
-    for (int i = tid; i < M; i += nt) mx = fmaxf(mx, (r[i] - mu) * scale);
-    mx = block_reduce<true>(mx, red);
-    float se = 0.0f;
-    for (int i = tid; i < M; i += nt) se += expf((r[i] - mu) * scale - mx);
-    se = block_reduce<false>(se, red);
-    const float inv = 1.0f / se;
-    for (int i = tid; i < M; i += nt) w[i] = expf((r[i] - mu) * scale - mx) * inv;
-}
-
-// du_out[e] = os * (du_in[e] * ms + sigma * sum_m w[m] eps[e][m]); one wave per row.
-template <bool STAGED, bool VEC>
-__global__ void __launch_bounds__(256) k_reduce_update(const float* __restrict__ eps,
-                                                       const float* __restrict__ w,
-                                                       const float* __restrict__ du_in,
-                                                       float* __restrict__ du_out, int D, int M,
-                                                       float ms, float sigma, float os) {
+// Softmax weights (Section IV-B, p_0 proportional to exp(r/lambda) of the
+// batch-normalised rewards) and the one-step update (Eq. mbd-denoising):
+// every workgroup combines the reward statistics, stages the unnormalised
+// weights exp(z_m - z_max) in LDS with their sum, then reduces rows of eps,
+// one wave per row, and applies the normaliser once per row.
+template <bool VEC>
+__global__ void __launch_bounds__(256) k_softmax_update(const UpdateArgs a) {
     extern __shared__ float wl[];
+    __shared__ float4 red4[4];
+    __shared__ float reds[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    const float* wsrc = w;
-    if (STAGED) {
-        for (int i = tid; i < M; i += blockDim.x) wl[i] = w[i];
-        __syncthreads();
-        wsrc = wl;
+    const int M = a.M;
+    float4 st = make_float4(0.0f, 0.0f, 0.0f, -INFINITY);
+    for (int i = tid; i < a.P; i += blockDim.x) st = chan_combine(st, a.partials[i]);
+    st = wave_combine(st);
+    if (lane == 0) red4[wave] = st;
+    __syncthreads();
+    st = red4[0];
+    for (int w = 1; w < nw; ++w) st = chan_combine(st, red4[w]);
+    const bool bad = !isfinite(st.y) || !isfinite(st.z) || !isfinite(st.w);
+    float mu = 0.0f, scale = a.inv_lam;
+    if (a.normalize) {
+        mu = st.y;
+        scale = a.inv_lam / fmaxf(sqrtf(st.z / st.x), 1e-6f);
     }
-    for (int e = blockIdx.x * nw + wave; e < D; e += gridDim.x * nw) {
-        const float* row = eps + (size_t)e * M;
+    const float zmax = (st.w - mu) * scale;
+    float se = 0.0f;
+    for (int i = tid; i < M; i += blockDim.x) {
+        const float e = bad ? 1.0f : __expf((a.r[i] - mu) * scale - zmax);
+        wl[i] = e;
+        se += e;
+    }
+    se = wave_sum(se);
+    __syncthreads();
+    if (lane == 0) reds[wave] = se;
+    __syncthreads();
+    se = reds[0];
+    for (int w = 1; w < nw; ++w) se += reds[w];
+    const float inv_se = 1.0f / se;
+    if (blockIdx.x == 0) {
+        if (a.w_out)
+            for (int i = tid; i < M; i += blockDim.x) a.w_out[i] = wl[i] * inv_se;
+        if (bad && tid == 0 && a.status) *a.status = -4;
+    }
+    const float s_inv = a.sigma * inv_se;
+    for (int e = blockIdx.x * nw + wave; e < a.D; e += gridDim.x * nw) {
+        const float* row = a.eps + (size_t)e * M;
         float acc = 0.0f;
         if (VEC) {
-            const float4* r4 = reinterpret_cast<const float4*>(row);
-            const float4* w4 = reinterpret_cast<const float4*>(wsrc);
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4* r4 = reinterpret_cast<const f4*>(row);
+            const f4* w4 = reinterpret_cast<const f4*>(wl);
             const int M4 = M >> 2;
-#pragma unroll 4
+#pragma unroll 8
             for (int i = lane; i < M4; i += 64) {
-                const float4 a = r4[i], b = w4[i];
-                acc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+                const f4 x = __builtin_nontemporal_load(r4 + i);
+                const f4 b = w4[i];
+                acc += x.x * b.x + x.y * b.y + x.z * b.z + x.w * b.w;
             }
         } else {
-            for (int i = lane; i < M; i += 64) acc += row[i] * wsrc[i];
+            for (int i = lane; i < M; i += 64) acc += row[i] * wl[i];
         }
         acc = wave_sum(acc);
-        if (lane == 0) du_out[e] = os * (du_in[e] * ms + sigma * acc);
+        if (lane == 0) a.du_out[e] = a.os * (a.du_in[e] * a.ms + s_inv * acc);
     }
 }
 
@@ -369,7 +492,7 @@ __global__ void __launch_bounds__(256) k_apply_final(const FinalArgs a) {
         float d0s = 0.0f;
 #pragma unroll
         for (int c = 0; c < DP; ++c) d0s += (x[c] - g[c]) * (x[c] - g[c]);
-        const float inv_d0 = 1.0f / fmaxf(sqrtf(d0s), a.d0_floor);
+        const float inv_d0 = 1.0f / fmaxf(fast_sqrt(d0s), a.d0_floor);
         float* tr = a.traj + (size_t)k * (T + 1) * DX;
 #pragma unroll
         for (int c = 0; c < DX; ++c) tr[c] = x[c];
@@ -383,35 +506,34 @@ __global__ void __launch_bounds__(256) k_apply_final(const FinalArgs a) {
             float d2 = 0.0f;
 #pragma unroll
             for (int c = 0; c < DP; ++c) d2 += (x[c] - g[c]) * (x[c] - g[c]);
-            const float dist = sqrtf(d2);
+            const float dist = fast_sqrt(d2);
             gacc += 1.0f - dist * inv_d0;
             at_goal += dist <= a.goal_tol;
             if (t == T - 1) term_bad = dist > a.goal_tol;
         }
     }
     __syncthreads();
+    // pair checks of every (step, robot) spread over the whole workgroup
     int safe_cnt = 0, hit_cnt = 0, unsafe = 0;
-    if (tid < n) {
-        const int k = tid;
-        for (int t = 1; t <= T; ++t) {
-            float pk[DP];
+    for (int idx = tid; idx < T * n; idx += blockDim.x) {
+        const int t = idx / n + 1, k = idx - (idx / n) * n;
+        float pk[DP];
 #pragma unroll
-            for (int c = 0; c < DP; ++c) pk[c] = a.traj[((size_t)k * (T + 1) + t) * DX + c];
-            int partners = 0;
-            for (int l = 0; l < n; ++l) {
-                if (l == k) continue;
-                float pl[DP];
+        for (int c = 0; c < DP; ++c) pk[c] = a.traj[((size_t)k * (T + 1) + t) * DX + c];
+        int partners = 0;
+        for (int l = 0; l < n; ++l) {
+            if (l == k) continue;
+            float pl[DP];
 #pragma unroll
-                for (int c = 0; c < DP; ++c) pl[c] = a.traj[((size_t)l * (T + 1) + t) * DX + c];
-                const float d2 = pair_d2<DP>(pk, pl);
-                if (d2 <= a.thr2) {
-                    ++partners;
-                    if (k < l) ++hit_cnt;
-                }
-                if (d2 <= a.safe2) unsafe = 1;
+            for (int c = 0; c < DP; ++c) pl[c] = a.traj[((size_t)l * (T + 1) + t) * DX + c];
+            const float d2 = pair_d2<DP>(pk, pl);
+            if (d2 <= a.thr2) {
+                ++partners;
+                if (k < l) ++hit_cnt;
             }
-            safe_cnt += partners > 0;
+            if (d2 <= a.safe2) unsafe = 1;
         }
+        safe_cnt += partners > 0;
     }
     red_g[tid] = gacc;
     red_s[tid] = safe_cnt;
@@ -422,7 +544,7 @@ __global__ void __launch_bounds__(256) k_apply_final(const FinalArgs a) {
     if (tid == 0) {
         float gs = 0.0f;
         int ss = 0, hs = 0, os = 0, bad = 0;
-        for (int i = 0; i < n; ++i) {
+        for (int i = 0; i < (int)blockDim.x; ++i) {
             gs += red_g[i];
             ss += red_s[i];
             hs += red_h[i];

@@ -222,7 +222,7 @@ def test_denoise_iteration_chain_and_graph(L):
         fin = ombd.apply_deformation(p, x0, g, u_base, _np(du0))
         assert abs(st["reward"] - fin["r"]) <= FINAL_RTOL * abs(fin["r"])
         assert st["hits"] == fin["hits"] and st["success"] == fin["success"]
-        assert abs(st["objective"] - fin["objective"]) < 1e-9
+        assert abs(st["objective"] - fin["objective"]) < 1e-6  # FP32 ratio of counts
         assert np.allclose(_np(traj), fin["x"], rtol=0, atol=2e-6 * p.horizon * 5)
 
 
@@ -300,3 +300,23 @@ def test_invalid_arguments_raise(L):
                        torch.zeros(p.D, device="cuda"), p.n_steps + 1)
     with pytest.raises(L.D4Error):
         L.Context(p.replace(temperature=0.0))
+
+
+def test_aligned_and_streamed_noise_paths_agree(L):
+    """The whole-block (aligned) and per-element (streamed) draw paths of the
+    fused kernel produce the same draws and the same rewards."""
+    p, x0, g = W.holo3d_sphere(n=8, horizon=40, n_samples=256)
+    rng = np.random.default_rng(2)
+    ub = _cu(_rand_controls(rng, p, 1, spread=0.5)[0].reshape(-1))
+    du = _cu((rng.normal(size=p.D) * 0.3).astype(np.float32))
+    outs = []
+    for flag in (None, "1"):
+        if flag:
+            os.environ["D4_NO_ALIGNED"] = flag
+        try:
+            outs.append([_np(t) for t in L.sample_rollout_fitness(p, _cu(x0), _cu(g), ub, du, 1, 33)])
+        finally:
+            os.environ.pop("D4_NO_ALIGNED", None)
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-6)
+    assert np.array_equal(outs[0][2], outs[1][2])
