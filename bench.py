@@ -97,6 +97,37 @@ def cpu_baseline(name, target_s=10.0):
                       f"(sampling, FP64 rollout, reward, weighted update), {dt:.1f} s, single-threaded NumPy"}
 
 
+KERNEL_SOURCES = ["paper_2503_12204_amd/csrc/d4_device.hpp", "paper_2503_12204_amd/csrc/d4_kernels.hpp",
+                  "paper_2503_12204_amd/csrc/d4_api.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a copy calibration),
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_rollfit_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("    ") and ":" in line:
+                k, v = line.strip().split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def time_fused_kernel(L, p, x0, g, reps=30):
     """Average duration of the fused sample+rollout+reward kernel, bracketed by
     HIP events on the stream it is launched on (torch's current stream)."""
@@ -129,7 +160,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="only launch the fused kernel this many times (for counter runs)")
+    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the planner's hot path runs on a single device "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -175,7 +210,7 @@ def main():
     ops = ops_per_unit(p.dyn, p.n_robots) * p.n_robots * p.horizon * p.n_samples
     achieved = ops / t_k
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK, "traffic": stored_traffic(args.workload),
                 "kernel": "k_rollfit (fused sample+rollout+reward)", "kernel_us": t_k * 1e6,
                 "ops_per_unit": ops_per_unit(p.dyn, p.n_robots)}
     out = {
