@@ -167,6 +167,40 @@ int32_t d4_denoise_iter(d4_ctx* ctx, const d4_problem* p, const float* x0, const
                         float* u_base, uint32_t iter, float* traj_out, d4_stats* stats,
                         void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent problems advanced together.  Each instance
+ * runs exactly the iteration of d4_denoise_iter (Algorithm 2 loop body over
+ * Algorithm 1), with its own team size, horizon, dynamics, limits, start and
+ * goal; every instance must share n_samples, n_steps, temperature,
+ * beta_min/beta_max, flags and seed (instance_id tells their draws apart).
+ * One reward launch over all (instance, sample block) tiles, longest first,
+ * and one update launch over all (instance, row range) tiles per denoising
+ * step; the iteration replays one captured HIP graph.  With the default
+ * launch shapes an instance's results equal its own d4_denoise_iter run
+ * bit for bit.
+ * ------------------------------------------------------------------------ */
+typedef struct d4_batch d4_batch;
+
+/* probs: host array of `count` problems (copied).  Allocates the workspace:
+ * sum_j D_j * M floats of draws dominate.  D4_EINVAL if sampler settings
+ * differ between instances. */
+int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** batch);
+
+/* Host outputs (each may be NULL): per-instance float offsets of the packed
+ * start states (x0_off, [n_j][d_x]), goals (goal_off, [n_j][d_p]) and plans
+ * (u_off, [n_j][T_j][d_u]) in instance order, and totals[3] = their lengths. */
+int32_t d4_batch_layout(const d4_batch* batch, int64_t* x0_off, int64_t* goal_off, int64_t* u_off,
+                        int64_t* totals);
+
+/* One iteration for every instance.  x0_all, goal_all, u_all are packed
+ * device arrays laid out as d4_batch_layout reports; u_all is updated in
+ * place.  stats: host array of `count` entries, or NULL.  Calls on one batch
+ * must not overlap. */
+int32_t d4_batch_iter(d4_batch* batch, const float* x0_all, const float* goal_all, float* u_all,
+                      uint32_t iter, d4_stats* stats, void* stream);
+
+int32_t d4_batch_destroy(d4_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

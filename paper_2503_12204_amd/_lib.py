@@ -58,6 +58,10 @@ def _load():
         "d4_ctx_create": ([P, POINTER(c_void_p)], c_int32),
         "d4_ctx_destroy": ([c_void_p], c_int32),
         "d4_denoise_iter": ([c_void_p, P, fp, fp, fp, c_uint32, fp, POINTER(D4Stats), c_void_p], c_int32),
+        "d4_batch_create": ([P, c_int32, POINTER(c_void_p)], c_int32),
+        "d4_batch_layout": ([c_void_p, fp, fp, fp, fp], c_int32),
+        "d4_batch_iter": ([c_void_p, fp, fp, fp, c_uint32, POINTER(D4Stats), c_void_p], c_int32),
+        "d4_batch_destroy": ([c_void_p], c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -233,3 +237,73 @@ def plan(p: Problem, x0, goal, iterations: int, u_init=None, stop_on_success=Fal
     finally:
         ctx.close()
     return u, hist
+
+
+def _stats_dict(s):
+    return dict(reward=s.reward, objective=s.objective, hits=s.hits, robots_hit=s.robots_hit,
+                success=bool(s.success), status=s.status)
+
+
+class BatchContext:
+    """Owns a d4_batch: many problems sharing the sampler settings, advanced together.
+
+    Inputs are lists of per-instance arrays; they are packed into device
+    arrays in the library's layout (offsets from d4_batch_layout)."""
+
+    def __init__(self, probs, x0s, goals):
+        import numpy as np
+        self.probs = list(probs)
+        n = len(self.probs)
+        arr = (D4Problem * n)(*[to_c(p) for p in self.probs])
+        self._arr = arr
+        h = c_void_p()
+        _check(_lib.d4_batch_create(arr, n, ctypes.byref(h)))
+        self._h = h
+        off = [np.zeros(n, dtype=np.int64) for _ in range(3)]
+        tot = np.zeros(3, dtype=np.int64)
+        _check(_lib.d4_batch_layout(h, *[c_void_p(o.ctypes.data) for o in off], c_void_p(tot.ctypes.data)))
+        self.x0_off, self.goal_off, self.u_off = off
+        self.totals = tot
+        self.x0 = self._pack(x0s, self.x0_off, tot[0])
+        self.goal = self._pack(goals, self.goal_off, tot[1])
+        self.u = torch.zeros(int(tot[2]), dtype=torch.float32, device="cuda")
+        self._stats = (D4Stats * n)()
+
+    @staticmethod
+    def _pack(arrays, offsets, total):
+        import numpy as np
+        flat = np.zeros(int(total), dtype=np.float32)
+        for a, o in zip(arrays, offsets):
+            a = np.asarray(a, dtype=np.float32).ravel()
+            flat[int(o):int(o) + a.size] = a
+        return torch.as_tensor(flat, device="cuda")
+
+    def plan_of(self, j):
+        """Instance j's plan [n][T][d_u] as a view of the packed device array."""
+        p = self.probs[j]
+        o = int(self.u_off[j])
+        return self.u[o:o + p.D].view(p.n_robots, p.horizon, p.du)
+
+    def set_plans(self, plans):
+        import numpy as np
+        self.u.copy_(self._pack(plans, self.u_off, self.totals[2]))
+
+    def iterate(self, iteration: int, sync=True):
+        """One iteration of every instance; returns per-instance stats when sync."""
+        _check(_lib.d4_batch_iter(self._h, _dev(self.x0), _dev(self.goal), _dev(self.u), iteration,
+                                  self._stats if sync else None, _stream()))
+        if not sync:
+            return None
+        torch.cuda.current_stream().synchronize()
+        return [_stats_dict(s) for s in self._stats]
+
+    def close(self):
+        if self._h:
+            _lib.d4_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,329 @@
+// Host side of the batched form: many independent planning problems of
+// uneven team size, horizon and dynamics advanced together, one reward launch
+// and one update launch per denoising step over all instances, one graph per
+// iteration.
+#include "d4.h"
+#include "d4_host.hpp"
+
+using namespace d4;
+using namespace d4host;
+
+struct d4_batch {
+    int count;
+    int device;
+    std::vector<d4_problem> probs;
+    std::vector<BatchInst> insts;
+    std::vector<BatchTile> tiles;
+    std::vector<BatchRows> rows;
+    long long tot_x0, tot_goal, tot_u, tot_eps, tot_r, tot_part, tot_traj;
+    size_t lds_rollfit;
+    // device buffers
+    BatchInst* d_insts;
+    BatchTile* d_tiles;
+    BatchRows* d_rows;
+    float *x0, *goal, *u, *du_a, *du_b, *eps, *r, *traj, *stats;
+    int *hits, *status;
+    float4* partials;
+    uint32_t* iter;
+    bool captured;
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+bool same_sampler(const d4_problem& a, const d4_problem& b) {
+    return a.n_samples == b.n_samples && a.n_steps == b.n_steps && a.temperature == b.temperature &&
+           a.beta_min == b.beta_min && a.beta_max == b.beta_max && a.flags == b.flags && a.seed == b.seed;
+}
+
+// Relative cost of one reward tile: steps times the per-lane work of a step.
+double tile_cost(const d4_problem& p) {
+    const Shape s = shape_of(p.dyn);
+    const double dyn_ops = p.dyn == UNICYCLE ? 13 : 5 * s.dp;
+    return (double)p.horizon * (s.du * 66.0 + dyn_ops + (2 * s.dp + 3) * (1 + (p.n_robots - 1) / 2.0) + 4);
+}
+
+void free_batch(d4_batch* b) {
+    void* ptrs[] = {b->d_insts, b->d_tiles, b->d_rows, b->x0,     b->goal,  b->u,      b->du_a,
+                    b->du_b,    b->eps,     b->r,      b->traj,   b->stats, b->hits,   b->status,
+                    b->partials, b->iter};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+constexpr int ROWS_PER_TILE = 64;
+
+int enqueue_batch_iteration(d4_batch* b, hipStream_t st) {
+    const d4_problem& p0 = b->probs[0];
+    const Schedule sc = make_schedule(&p0);
+    const int M = p0.n_samples;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((b->tot_u + 255) / 256)), dim3(256), 0, st, b->du_a,
+                       (int)b->tot_u, 0.0f);
+    HIP_LAUNCH_CHECK("k_fill");
+    float* du_cur = b->du_a;
+    float* du_nxt = b->du_b;
+    BatchStepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.insts = b->d_insts;
+    a.tiles = b->d_tiles;
+    a.x0 = b->x0;
+    a.goal = b->goal;
+    a.u = b->u;
+    a.eps = b->eps;
+    a.r = b->r;
+    a.hits = b->hits;
+    a.partials = b->partials;
+    a.iter_dev = b->iter;
+    a.M = M;
+    a.key0 = (uint32_t)(p0.seed & 0xFFFFFFFFull);
+    a.key1 = (uint32_t)(p0.seed >> 32);
+    a.flags = p0.flags;
+    BatchUpdArgs ua;
+    std::memset(&ua, 0, sizeof ua);
+    ua.insts = b->d_insts;
+    ua.rows = b->d_rows;
+    ua.eps = b->eps;
+    ua.r = b->r;
+    ua.partials = b->partials;
+    ua.status = b->status;
+    ua.M = M;
+    ua.inv_lam = 1.0f / p0.temperature;
+    ua.normalize = (p0.flags & FLAG_NORMALIZE) ? 1 : 0;
+    allow_lds(k_batch_rollfit, b->lds_rollfit);
+    for (int i = p0.n_steps; i >= 1; --i) {
+        a.du_in = du_cur;
+        a.step = (uint32_t)i;
+        a.mean_scale = sc.ms[i];
+        a.sigma = sc.sigma[i];
+        hipLaunchKernelGGL(k_batch_rollfit, dim3((unsigned)b->tiles.size()), dim3(256), b->lds_rollfit, st, a);
+        HIP_LAUNCH_CHECK("k_batch_rollfit");
+        ua.du_in = du_cur;
+        ua.du_out = du_nxt;
+        ua.ms = sc.ms[i];
+        ua.sigma = sc.sigma[i];
+        ua.os = sc.os[i];
+        hipLaunchKernelGGL(k_batch_update, dim3((unsigned)b->rows.size()), dim3(256), (size_t)M * 4, st, ua);
+        HIP_LAUNCH_CHECK("k_batch_update");
+        std::swap(du_cur, du_nxt);
+    }
+    BatchFinalArgs f;
+    f.insts = b->d_insts;
+    f.u = b->u;
+    f.du0 = du_cur;
+    f.x0 = b->x0;
+    f.goal = b->goal;
+    f.traj = b->traj;
+    f.stats = b->stats;
+    f.status = b->status;
+    f.flags = p0.flags;
+    hipLaunchKernelGGL(k_batch_final, dim3((unsigned)b->count), dim3(256), 0, st, f);
+    HIP_LAUNCH_CHECK("k_batch_final");
+    return D4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) {
+    if (!probs || count < 1) return fail(D4_EINVAL, "need at least one problem");
+    if (!out) return fail(D4_EINVAL, "batch out-pointer is NULL");
+    for (int j = 0; j < count; ++j) {
+        int rc = validate(&probs[j]);
+        if (rc) return fail(rc, "instance %d: %s", j, g_err.c_str());
+        if (!same_sampler(probs[j], probs[0]))
+            return fail(D4_EINVAL, "instance %d: sampler settings differ from instance 0", j);
+    }
+    if (probs[0].n_samples > 16384)
+        return fail(D4_EUNSUPPORTED, "n_samples %d above the 16384 weights one workgroup stages", probs[0].n_samples);
+    d4_batch* b = new (std::nothrow) d4_batch();
+    if (!b) return fail(D4_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->probs.assign(probs, probs + count);
+    HIP_TRY(hipGetDevice(&b->device));
+    const long long M = probs[0].n_samples;
+    long long ox = 0, og = 0, ou = 0, oe = 0, orr = 0, op = 0, ot = 0;
+    size_t lds = 0;
+    std::vector<std::pair<double, BatchTile>> tl;
+    for (int j = 0; j < count; ++j) {
+        const d4_problem& p = probs[j];
+        const Shape s = shape_of(p.dyn);
+        const Tile t = default_tile(p.dyn, p.n_robots);
+        BatchInst in;
+        std::memset(&in, 0, sizeof in);
+        in.n = p.n_robots;
+        in.T = p.horizon;
+        in.dyn = p.dyn;
+        in.S = t.S;
+        in.Tb = t.Tb;
+        in.mode = aligned_ok(&p, t) ? MODE_ALIGNED : MODE_STREAM;
+        in.D = p.n_robots * p.horizon * s.du;
+        in.P = (int)((M + t.S - 1) / t.S);
+        in.x0 = ox;
+        in.goal = og;
+        in.u = ou;
+        in.eps = oe;
+        in.r = orr;
+        in.part = op;
+        in.traj = ot;
+        in.thr2 = thr2_reward(&p);
+        const double s2 = 2.0 * (double)p.robot_radius;
+        in.safe2 = (float)(s2 * s2);
+        in.w_safe = p.w_safe;
+        in.d0_floor = p.d0_floor;
+        in.goal_tol = p.goal_tol;
+        for (int d = 0; d < 3; ++d) {
+            in.ulo[d] = p.u_lo[d];
+            in.uhi[d] = p.u_hi[d];
+        }
+        in.sc = step_consts(&p);
+        in.inst_id = p.instance_id;
+        b->insts.push_back(in);
+        const double cost = tile_cost(p);
+        for (int q = 0; q < in.P; ++q) tl.push_back({cost, BatchTile{j, q * t.S, q}});
+        for (int e0 = 0; e0 < in.D; e0 += ROWS_PER_TILE)
+            b->rows.push_back(BatchRows{j, e0, std::min(in.D, e0 + ROWS_PER_TILE)});
+        lds = std::max(lds, rollfit_lds(&p, t));
+        ox += (long long)p.n_robots * s.dx;
+        og += (long long)p.n_robots * s.dp;
+        ou += in.D;
+        oe += (long long)in.D * M;
+        orr += M;
+        op += in.P;
+        ot += (long long)p.n_robots * (p.horizon + 1) * s.dx;
+    }
+    if (lds > 160 * 1024) {
+        delete b;
+        return fail(D4_EUNSUPPORTED, "reward tiles need %zu bytes of LDS", lds);
+    }
+    // longest tiles first: the dispatcher hands workgroups out in order
+    std::stable_sort(tl.begin(), tl.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (auto& t : tl) b->tiles.push_back(t.second);
+    b->tot_x0 = ox;
+    b->tot_goal = og;
+    b->tot_u = ou;
+    b->tot_eps = oe;
+    b->tot_r = orr;
+    b->tot_part = op;
+    b->tot_traj = ot;
+    b->lds_rollfit = lds;
+    if (ou >= (1ll << 31) || oe >= (1ll << 40)) {
+        delete b;
+        return fail(D4_EUNSUPPORTED, "batch too large");
+    }
+    struct {
+        void** ptr;
+        size_t bytes;
+    } allocs[] = {
+        {(void**)&b->d_insts, sizeof(BatchInst) * b->insts.size()},
+        {(void**)&b->d_tiles, sizeof(BatchTile) * b->tiles.size()},
+        {(void**)&b->d_rows, sizeof(BatchRows) * b->rows.size()},
+        {(void**)&b->x0, 4 * (size_t)ox},
+        {(void**)&b->goal, 4 * (size_t)og},
+        {(void**)&b->u, 4 * (size_t)ou},
+        {(void**)&b->du_a, 4 * (size_t)ou},
+        {(void**)&b->du_b, 4 * (size_t)ou},
+        {(void**)&b->eps, 4 * (size_t)oe},
+        {(void**)&b->r, 4 * (size_t)orr},
+        {(void**)&b->hits, 4 * (size_t)orr},
+        {(void**)&b->partials, sizeof(float4) * (size_t)op},
+        {(void**)&b->traj, 4 * (size_t)ot},
+        {(void**)&b->stats, sizeof(d4_stats) * (size_t)count},
+        {(void**)&b->status, 4 * (size_t)count},
+        {(void**)&b->iter, 4},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
+            free_batch(b);
+            delete b;
+            return fail(D4_ENOMEM, "hipMalloc of %zu bytes failed", a.bytes);
+        }
+    }
+    hipError_t e1 = hipMemcpy(b->d_insts, b->insts.data(), sizeof(BatchInst) * b->insts.size(), hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(b->d_tiles, b->tiles.data(), sizeof(BatchTile) * b->tiles.size(), hipMemcpyHostToDevice);
+    hipError_t e3 = hipMemcpy(b->d_rows, b->rows.data(), sizeof(BatchRows) * b->rows.size(), hipMemcpyHostToDevice);
+    hipError_t e4 = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+        free_batch(b);
+        delete b;
+        return fail(D4_EHIP, "batch set-up copies failed");
+    }
+    *out = b;
+    return D4_OK;
+}
+
+int32_t d4_batch_layout(const d4_batch* b, int64_t* x0_off, int64_t* goal_off, int64_t* u_off, int64_t* totals) {
+    if (!b) return fail(D4_EINVAL, "batch is NULL");
+    for (int j = 0; j < b->count; ++j) {
+        if (x0_off) x0_off[j] = b->insts[j].x0;
+        if (goal_off) goal_off[j] = b->insts[j].goal;
+        if (u_off) u_off[j] = b->insts[j].u;
+    }
+    if (totals) {
+        totals[0] = b->tot_x0;
+        totals[1] = b->tot_goal;
+        totals[2] = b->tot_u;
+    }
+    return D4_OK;
+}
+
+int32_t d4_batch_iter(d4_batch* b, const float* x0_all, const float* goal_all, float* u_all, uint32_t iter,
+                      d4_stats* stats, void* stream) {
+    if (!b) return fail(D4_EINVAL, "batch is NULL");
+    NEED(x0_all);
+    NEED(goal_all);
+    NEED(u_all);
+    if (iter > 65535u) return fail(D4_EINVAL, "iter %u does not fit 16 bits", iter);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != b->device) return fail(D4_EINVAL, "batch was created on device %d, current is %d", b->device, dev);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(b->x0, x0_all, 4 * (size_t)b->tot_x0, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->goal, goal_all, 4 * (size_t)b->tot_goal, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->u, u_all, 4 * (size_t)b->tot_u, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_fill_int, dim3((b->count + 255) / 256), dim3(256), 0, st, b->status, b->count, 0);
+    HIP_LAUNCH_CHECK("k_fill_int");
+    hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, st, b->iter, iter, b->status);
+    HIP_LAUNCH_CHECK("k_set_iter");
+    const char* ng = std::getenv("D4_NO_GRAPH");
+    if (ng && ng[0] == '1') {
+        int rc = enqueue_batch_iteration(b, st);
+        if (rc) return rc;
+    } else {
+        if (!b->captured) {
+            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_batch_iteration(b, b->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(b->cap_stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (ec != hipSuccess) return fail(D4_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+            b->graph = g;
+            HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->captured = true;
+        }
+        HIP_TRY(hipGraphLaunch(b->exec, st));
+    }
+    HIP_TRY(hipMemcpyAsync(u_all, b->u, 4 * (size_t)b->tot_u, hipMemcpyDeviceToDevice, st));
+    if (stats)
+        HIP_TRY(hipMemcpyAsync(stats, b->stats, sizeof(d4_stats) * (size_t)b->count, hipMemcpyDeviceToHost, st));
+    return D4_OK;
+}
+
+int32_t d4_batch_destroy(d4_batch* b) {
+    if (!b) return D4_OK;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    free_batch(b);
+    delete b;
+    return D4_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+// Host-side helpers shared by the C-ABI sources: error reporting, argument
+// validation, the noise schedule and the launch shapes of the reward kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "d4.h"
+#include "d4_kernels.hpp"
+
+namespace d4host {
+
+using namespace d4;
+
+inline thread_local std::string g_err;
+
+inline int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(D4_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+#define HIP_LAUNCH_CHECK(name)                                                         \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return fail(D4_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Shape {
+    int dx, du, dp;
+};
+
+inline Shape shape_of(int dyn) {
+    switch (dyn) {
+        case HOLO2D: return {4, 2, 2};
+        case HOLO3D: return {6, 3, 3};
+        default: return {3, 2, 2};
+    }
+}
+
+inline bool finite_f(float v) { return std::isfinite(v); }
+
+inline int validate(const d4_problem* p) {
+    if (!p) return fail(D4_EINVAL, "problem is NULL");
+    if (p->dyn < 0 || p->dyn > 2) return fail(D4_EINVAL, "dyn %d is not a known model", p->dyn);
+    if (p->n_robots < 1 || p->n_robots > 32)
+        return fail(D4_EINVAL, "n_robots %d outside 1..32", p->n_robots);
+    if (p->horizon < 1) return fail(D4_EINVAL, "horizon %d < 1", p->horizon);
+    if (p->n_samples < 1) return fail(D4_EINVAL, "n_samples %d < 1", p->n_samples);
+    if (p->n_steps < 1 || p->n_steps > 65535)
+        return fail(D4_EINVAL, "n_steps %d outside 1..65535", p->n_steps);
+    if (!(p->dt > 0.0f) || !finite_f(p->dt)) return fail(D4_EINVAL, "dt must be positive");
+    if (!(p->temperature > 0.0f) || !finite_f(p->temperature))
+        return fail(D4_EINVAL, "temperature must be positive");
+    if (!(p->robot_radius >= 0.0f) || !(p->safety_margin >= 0.0f) || !finite_f(p->robot_radius) ||
+        !finite_f(p->safety_margin))
+        return fail(D4_EINVAL, "robot_radius and safety_margin must be >= 0");
+    if (!(p->d0_floor > 0.0f)) return fail(D4_EINVAL, "d0_floor must be positive");
+    if (!finite_f(p->w_safe) || !finite_f(p->beta_min) || !finite_f(p->beta_max))
+        return fail(D4_EINVAL, "non-finite weight or schedule");
+    if (!(p->beta_min > 0.0f) || !(p->beta_max < 1.0f) || p->beta_min > p->beta_max)
+        return fail(D4_EINVAL, "need 0 < beta_min <= beta_max < 1");
+    const Shape s = shape_of(p->dyn);
+    for (int d = 0; d < s.du; ++d)
+        if (!(p->u_lo[d] <= p->u_hi[d]) || !finite_f(p->u_lo[d]) || !finite_f(p->u_hi[d]))
+            return fail(D4_EINVAL, "control box %d is empty or non-finite", d);
+    if (p->dyn != UNICYCLE && !(p->v_max >= 0.0f)) return fail(D4_EINVAL, "v_max must be >= 0");
+    const double D = (double)p->n_robots * p->horizon * s.du;
+    if (D * p->n_samples > 4.0e9) return fail(D4_EUNSUPPORTED, "D*M = %.0f too large", D * p->n_samples);
+    if ((D + 3) / 4 > 65535.0) return fail(D4_EUNSUPPORTED, "D = %.0f too large for one launch", D);
+    return D4_OK;
+}
+
+inline int need(const void* ptr, const char* name) {
+    if (!ptr) return fail(D4_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(ptr) & 3u) return fail(D4_EINVAL, "%s is not 4-byte aligned", name);
+    return D4_OK;
+}
+
+#define NEED(ptr)                                \
+    do {                                         \
+        int rc_ = need((ptr), #ptr);             \
+        if (rc_) return rc_;                     \
+    } while (0)
+
+struct Schedule {
+    std::vector<float> ms, sigma, os;  // index 0..N
+};
+
+// Linear betas over i = 1..N (both ends included), alpha-bar products in FP64.
+inline Schedule make_schedule(const d4_problem* p) {
+    const int N = p->n_steps;
+    Schedule s;
+    s.ms.assign(N + 1, 0.0f);
+    s.sigma.assign(N + 1, 0.0f);
+    s.os.assign(N + 1, 0.0f);
+    double ab_prev = 1.0;
+    for (int i = 1; i <= N; ++i) {
+        const double beta = N == 1 ? (double)p->beta_min
+                                   : (double)p->beta_min +
+                                         ((double)p->beta_max - (double)p->beta_min) * (i - 1) / (N - 1);
+        const double ab = ab_prev * (1.0 - beta);
+        s.ms[i] = (float)(1.0 / std::sqrt(ab));
+        s.sigma[i] = (float)std::sqrt(1.0 / ab - 1.0);
+        s.os[i] = (float)std::sqrt(ab_prev);
+        ab_prev = ab;
+    }
+    return s;
+}
+
+inline float thr2_reward(const d4_problem* p) {
+    const double thr = 2.0 * (double)p->robot_radius + (double)p->safety_margin;
+    return (float)(thr * thr);
+}
+
+inline StepConsts step_consts(const d4_problem* p) {
+    StepConsts c;
+    c.dt = p->dt;
+    c.hdt = (float)(0.5 * p->dt);
+    c.hdt2 = (float)(0.5 * (double)p->dt * (double)p->dt);
+    c.dt6 = (float)((double)p->dt / 6.0);
+    c.vmax = p->v_max;
+    return c;
+}
+
+struct Tile {
+    int S, Tb;
+};
+
+// Samples per workgroup and time-block length of the reward kernels.  One
+// rule serves the single-problem and the batched kernels (workgroups of at most
+// 256 lanes), so a batched instance reproduces its single-problem run bit for
+// bit: S = min(64, floor(256 / n)) samples, and a time block that keeps the
+// double-buffered positions near 32 KiB, in whole draw chunks.
+inline Tile default_tile(int dyn, int n) {
+    int S = std::min(64, 256 / n);
+    const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
+    const int per_step = 2 * n * S * slot;
+    int Tb = (32 * 1024) / per_step;
+    const int cs = shape_of(dyn).du == 2 ? 2 : 4;
+    Tb = std::max(cs, std::min(16, Tb / cs * cs));
+    return {S, Tb};
+}
+
+inline Tile pick_tile(const d4_problem* p) {
+    const int n = p->n_robots;
+    Tile t = default_tile(p->dyn, n);
+    int S = t.S, Tb = t.Tb;
+    const char* env = std::getenv("D4_TILE_S");
+    if (env) {
+        int v = std::atoi(env);
+        if (v >= 1 && v <= 64 && v * n <= 1024) S = v;
+    }
+    const char* envt = std::getenv("D4_TILE_TB");
+    if (envt) {
+        int v = std::atoi(envt);
+        if (v >= 1 && v <= 64) Tb = v;
+    }
+    return {S, Tb};
+}
+
+inline size_t rollfit_lds(const d4_problem* p, Tile t) {
+    const Shape s = shape_of(p->dyn);
+    const size_t n = p->n_robots;
+    const size_t slot = s.dp == 3 ? 16 : 8;
+    const size_t a = (size_t)2 * t.Tb * n * t.S * slot + (size_t)2 * t.Tb * t.S * 4;
+    const size_t b = (size_t)3 * n * t.S * 4;
+    return a > b ? a : b;
+}
+
+// Steps per noise chunk of the aligned fused kernel (whole Philox blocks).
+inline int chunk_steps(int du) { return du == 2 ? 2 : 4; }
+
+inline bool aligned_ok(const d4_problem* p, Tile t) {
+    const int du = shape_of(p->dyn).du;
+    return ((p->horizon * du) % 4 == 0) && (t.Tb % chunk_steps(du) == 0) && !std::getenv("D4_NO_ALIGNED");
+}
+
+inline RollFitArgs base_args(const d4_problem* p, Tile tile) {
+    RollFitArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = p->n_robots;
+    a.T = p->horizon;
+    a.M = p->n_samples;
+    a.S = tile.S;
+    a.Tb = tile.Tb;
+    a.thr2 = thr2_reward(p);
+    a.w_safe = p->w_safe;
+    a.d0_floor = p->d0_floor;
+    for (int d = 0; d < 3; ++d) {
+        a.ulo[d] = p->u_lo[d];
+        a.uhi[d] = p->u_hi[d];
+    }
+    a.sc = step_consts(p);
+    a.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.inst = p->instance_id;
+    a.flags = p->flags;
+    return a;
+}
+
+// Dynamic LDS above 64 KiB must be enabled per kernel (gfx950: 160 KiB per CU).
+template <typename K>
+inline void allow_lds(K kernel, size_t lds) {
+    if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+}  // namespace d4host

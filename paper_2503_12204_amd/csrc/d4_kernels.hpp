@@ -94,21 +94,25 @@ struct Chunk {
 // Reward of one (sample, robot) lane per step block; see the mapping notes above.
 // MODE_ALIGNED requires T * d_u % 4 == 0 and Tb a multiple of Chunk::STEPS so
 // that every chunk of a robot's elements starts on a Philox block boundary.
+// One tile: samples m0 .. m0+S-1 of one problem, lanes tid < n*S (the rest of
+// the workgroup idles through the barriers).  Writes the tile's reward
+// statistics to partials[part] when partials is set.
 template <int DYN, int MODE>
-__global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
+__device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int part, float* lds) {
     using DY = Dyn<DYN>;
     constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
     using PS = PosSlot<DP>;
     using PT = typename PS::T;
     constexpr bool FROM_X = MODE == MODE_FROM_X;
-    extern __shared__ float lds[];
     const int n = a.n, T = a.T, M = a.M, S = a.S, Tb = a.Tb;
     const int tid = threadIdx.x;
-    const int k = tid / S;
-    const int ms = tid - k * S;
-    const int m = blockIdx.x * S + ms;
-    const bool live = m < M;
-    const int mc = live ? m : M - 1;
+    const int k_raw = tid / S;
+    const bool active = k_raw < n;
+    const int k = active ? k_raw : n - 1;
+    const int ms = tid - k_raw * S;
+    const int m = m0 + ms;
+    const bool live = active && m < M;
+    const int mc = m < M ? m : M - 1;
     PT* pos = reinterpret_cast<PT*>(lds);                                        // [2][Tb][n][S]
     uint32_t* mask = reinterpret_cast<uint32_t*>(pos + 2 * Tb * n * S);          // [2][Tb][S]
 
@@ -143,7 +147,7 @@ __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
         uhi[d] = a.uhi[d];
     }
     const float sigma = a.sigma, mscale = a.mean_scale;
-    const int jmax = ((n - 1) >> 1) + ((((n & 1) == 0) && (k < (n >> 1))) ? 1 : 0);
+    const int jmax = active ? ((n - 1) >> 1) + ((((n & 1) == 0) && (k < (n >> 1))) ? 1 : 0) : 0;
     const bool pairs_mode = (a.flags & FLAG_SAFE_PAIRS) != 0;
     const size_t Ms = (size_t)M;
 
@@ -153,7 +157,7 @@ __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
 #pragma unroll
         for (int c = 0; c < DP; ++c) dist2 += (x[c] - g[c]) * (x[c] - g[c]);
         goal_acc += 1.0f - fast_sqrt(dist2) * inv_d0;
-        pos[((buf * Tb + tt) * n + k) * S + ms] = PS::pack(x);
+        if (active) pos[((buf * Tb + tt) * n + k) * S + ms] = PS::pack(x);
     };
 
     const int nblk = (T + Tb - 1) / Tb;
@@ -211,7 +215,7 @@ __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
                 after_step(buf, tt);
             }
         }
-        if (k == 0)
+        if (k_raw == 0)
             for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
         __syncthreads();
         for (int tt = 0; tt < tcount; ++tt) {
@@ -238,18 +242,21 @@ __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
             if (bits) atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));
         }
         __syncthreads();
-        for (int tt = 0; tt < tcount; ++tt) safe_cnt += (mask[(buf * Tb + tt) * S + ms] >> k) & 1u;
+        if (active)
+            for (int tt = 0; tt < tcount; ++tt) safe_cnt += (mask[(buf * Tb + tt) * S + ms] >> k) & 1u;
     }
 
     __syncthreads();
     float* rg = lds;
     int* rs = reinterpret_cast<int*>(lds + n * S);
     int* rh = rs + n * S;
-    rg[k * S + ms] = goal_acc;
-    rs[k * S + ms] = safe_cnt;
-    rh[k * S + ms] = hit_cnt;
+    if (active) {
+        rg[k * S + ms] = goal_acc;
+        rs[k * S + ms] = safe_cnt;
+        rh[k * S + ms] = hit_cnt;
+    }
     __syncthreads();
-    if (k == 0 && live) {
+    if (k_raw == 0 && live) {
         float gs = 0.0f;
         int ss = 0, hs = 0;
         for (int kk = 0; kk < n; ++kk) {
@@ -265,20 +272,26 @@ __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
         rg[ms] = rv;
     }
     if (a.partials && tid < 64) {
-        // statistics of this workgroup's rewards (S <= 64 lanes of wave 0)
-        const bool mine = tid < S && (blockIdx.x * S + tid) < M;
+        // statistics of this tile's rewards (S <= 64 lanes of wave 0)
+        const bool mine = tid < S && (m0 + tid) < M;
         const float rv = mine ? rg[tid] : 0.0f;
         const float cnt = wave_sum(mine ? 1.0f : 0.0f);
         const float mean = wave_sum(rv) / cnt;
         const float dv = mine ? rv - mean : 0.0f;
         const float m2 = wave_sum(dv * dv);
         const float mx = wave_max(mine ? rv : -INFINITY);
-        if (tid == 0) a.partials[blockIdx.x] = make_float4(cnt, mean, m2, mx);
+        if (tid == 0) a.partials[part] = make_float4(cnt, mean, m2, mx);
     }
 }
 
+template <int DYN, int MODE>
+__global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
+    extern __shared__ float lds[];
+    rollfit_tile<DYN, MODE>(a, blockIdx.x * a.S, blockIdx.x, lds);
+}
+
 // eps[e][m] for e < D, m < M; one lane per (Philox block, sample).
-__global__ void __launch_bounds__(256) k_noise(float* eps, int D, int M, uint32_t c2, uint32_t c3,
+static __global__ void __launch_bounds__(256) k_noise(float* eps, int D, int M, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int g = blockIdx.y;
@@ -347,7 +360,7 @@ __device__ __forceinline__ float4 wave_combine(float4 v) {
 
 // Reward statistics of consecutive S-sample chunks (S <= 64), computed exactly
 // as the fused kernel's tail computes them for its workgroups of S samples.
-__global__ void __launch_bounds__(64) k_reward_partials(const float* r, int M, int S, float4* partials) {
+static __global__ void __launch_bounds__(64) k_reward_partials(const float* r, int M, int S, float4* partials) {
     const int m = blockIdx.x * S + threadIdx.x;
     const bool mine = (int)threadIdx.x < S && m < M;
     const float rv = mine ? r[m] : 0.0f;
@@ -379,8 +392,8 @@ struct UpdateArgs {
 // weights exp(z_m - z_max) in LDS with their sum, then reduces rows of eps,
 // one wave per row, and applies the normaliser once per row.
 template <bool VEC>
-__global__ void __launch_bounds__(256) k_softmax_update(const UpdateArgs a) {
-    extern __shared__ float wl[];
+__device__ __forceinline__ void softmax_update_rows(const UpdateArgs& a, int e_begin, int e_step, int e_end,
+                                                    bool first, float* wl) {
     __shared__ float4 red4[4];
     __shared__ float reds[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
@@ -412,13 +425,13 @@ __global__ void __launch_bounds__(256) k_softmax_update(const UpdateArgs a) {
     se = reds[0];
     for (int w = 1; w < nw; ++w) se += reds[w];
     const float inv_se = 1.0f / se;
-    if (blockIdx.x == 0) {
+    if (first) {
         if (a.w_out)
             for (int i = tid; i < M; i += blockDim.x) a.w_out[i] = wl[i] * inv_se;
         if (bad && tid == 0 && a.status) *a.status = -4;
     }
     const float s_inv = a.sigma * inv_se;
-    for (int e = blockIdx.x * nw + wave; e < a.D; e += gridDim.x * nw) {
+    for (int e = e_begin + wave; e < e_end; e += e_step) {
         const float* row = a.eps + (size_t)e * M;
         float acc = 0.0f;
         if (VEC) {
@@ -440,12 +453,19 @@ __global__ void __launch_bounds__(256) k_softmax_update(const UpdateArgs a) {
     }
 }
 
-__global__ void k_fill(float* p, int n, float v) {
+template <bool VEC>
+__global__ void __launch_bounds__(256) k_softmax_update(const UpdateArgs a) {
+    extern __shared__ float wl[];
+    const int nw = blockDim.x >> 6;
+    softmax_update_rows<VEC>(a, blockIdx.x * nw, gridDim.x * nw, a.D, blockIdx.x == 0, wl);
+}
+
+static __global__ void k_fill(float* p, int n, float v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
-__global__ void k_set_iter(uint32_t* it, uint32_t v, int* status) {
+static __global__ void k_set_iter(uint32_t* it, uint32_t v, int* status) {
     *it = v;
     *status = 0;
 }
@@ -467,7 +487,7 @@ struct FinalArgs {
 
 // One block: apply the deformation, roll the plan out, score it.
 template <int DYN>
-__global__ void __launch_bounds__(256) k_apply_final(const FinalArgs a) {
+__device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
     using DY = Dyn<DYN>;
     constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
     __shared__ float red_g[256];
@@ -560,6 +580,190 @@ __global__ void __launch_bounds__(256) k_apply_final(const FinalArgs a) {
         si[4] = bad ? 0 : 1;
         si[5] = a.status ? *a.status : 0;
     }
+}
+
+template <int DYN>
+__global__ void __launch_bounds__(256) k_apply_final(const FinalArgs a) {
+    apply_final_body<DYN>(a);
+}
+
+// ------------------------------------------------------------- batched form
+// Many independent problems per launch.  Every instance shares the sample
+// count M, the schedule, the temperature, the flags and the Philox key; the
+// team size, horizon, dynamics and limits are its own.  Offsets count floats
+// (or samples) into packed arrays in instance order.
+struct BatchInst {
+    int n, T, dyn, S, Tb, mode, D, P;
+    long long x0, goal, u, eps, r, part, traj;
+    float thr2, safe2, w_safe, d0_floor, goal_tol;
+    float ulo[3], uhi[3];
+    StepConsts sc;
+    uint32_t inst_id;
+};
+struct BatchTile {   // samples m0 .. m0+S-1 of one instance
+    int inst, m0, part;
+};
+struct BatchRows {   // rows e0 .. e1-1 of one instance's update
+    int inst, e0, e1;
+};
+
+struct BatchStepArgs {
+    const BatchInst* insts;
+    const BatchTile* tiles;
+    const float* x0;
+    const float* goal;
+    const float* u;
+    const float* du_in;
+    float* eps;
+    float* r;
+    int* hits;
+    float4* partials;
+    const uint32_t* iter_dev;
+    int M;
+    uint32_t key0, key1, step, flags;
+    float mean_scale, sigma;
+};
+
+// Sampling + rollout + reward of one tile per workgroup (256 lanes).
+static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArgs b) {
+    extern __shared__ float lds[];
+    const BatchTile tl = b.tiles[blockIdx.x];
+    const BatchInst& in = b.insts[tl.inst];
+    RollFitArgs a;
+    a.x0 = b.x0 + in.x0;
+    a.goal = b.goal + in.goal;
+    a.u_base = b.u + in.u;
+    a.du_in = b.du_in + in.u;
+    a.xs = nullptr;
+    a.eps = b.eps + in.eps;
+    a.r = b.r + in.r;
+    a.hits = b.hits + in.r;
+    a.robots_hit = nullptr;
+    a.partials = b.partials + in.part;
+    a.iter_dev = b.iter_dev;
+    a.n = in.n;
+    a.T = in.T;
+    a.M = b.M;
+    a.S = in.S;
+    a.Tb = in.Tb;
+    a.mean_scale = b.mean_scale;
+    a.sigma = b.sigma;
+    a.thr2 = in.thr2;
+    a.w_safe = in.w_safe;
+    a.d0_floor = in.d0_floor;
+    for (int d = 0; d < 3; ++d) {
+        a.ulo[d] = in.ulo[d];
+        a.uhi[d] = in.uhi[d];
+    }
+    a.sc = in.sc;
+    a.key0 = b.key0;
+    a.key1 = b.key1;
+    a.step = b.step;
+    a.iter = 0;
+    a.inst = in.inst_id;
+    a.flags = b.flags;
+    const bool al = in.mode == MODE_ALIGNED;
+    switch (in.dyn) {
+        case HOLO2D:
+            if (al) rollfit_tile<HOLO2D, MODE_ALIGNED>(a, tl.m0, tl.part, lds);
+            else rollfit_tile<HOLO2D, MODE_STREAM>(a, tl.m0, tl.part, lds);
+            break;
+        case HOLO3D:
+            if (al) rollfit_tile<HOLO3D, MODE_ALIGNED>(a, tl.m0, tl.part, lds);
+            else rollfit_tile<HOLO3D, MODE_STREAM>(a, tl.m0, tl.part, lds);
+            break;
+        default:
+            if (al) rollfit_tile<UNICYCLE, MODE_ALIGNED>(a, tl.m0, tl.part, lds);
+            else rollfit_tile<UNICYCLE, MODE_STREAM>(a, tl.m0, tl.part, lds);
+            break;
+    }
+}
+
+struct BatchUpdArgs {
+    const BatchInst* insts;
+    const BatchRows* rows;
+    const float* eps;
+    const float* r;
+    const float4* partials;
+    const float* du_in;
+    float* du_out;
+    int* status;  // [count]
+    int M;
+    float inv_lam;
+    int normalize;
+    float ms, sigma, os;
+};
+
+// Softmax weights and the update of one row range per workgroup.
+static __global__ void __launch_bounds__(256) k_batch_update(const BatchUpdArgs b) {
+    extern __shared__ float wl[];
+    const BatchRows rt = b.rows[blockIdx.x];
+    const BatchInst& in = b.insts[rt.inst];
+    UpdateArgs a;
+    a.eps = b.eps + in.eps;
+    a.r = b.r + in.r;
+    a.partials = b.partials + in.part;
+    a.du_in = b.du_in + in.u;
+    a.du_out = b.du_out + in.u;
+    a.w_out = nullptr;
+    a.status = b.status + rt.inst;
+    a.D = in.D;
+    a.M = b.M;
+    a.P = in.P;
+    a.inv_lam = b.inv_lam;
+    a.normalize = b.normalize;
+    a.ms = b.ms;
+    a.sigma = b.sigma;
+    a.os = b.os;
+    softmax_update_rows<true>(a, rt.e0, blockDim.x >> 6, rt.e1, rt.e0 == 0, wl);
+}
+
+struct BatchFinalArgs {
+    const BatchInst* insts;
+    float* u;
+    const float* du0;
+    const float* x0;
+    const float* goal;
+    float* traj;
+    float* stats;        // [count][6]
+    const int* status;   // [count]
+    uint32_t flags;
+};
+
+// Apply, roll out and score one instance per workgroup.
+static __global__ void __launch_bounds__(256) k_batch_final(const BatchFinalArgs b) {
+    const BatchInst& in = b.insts[blockIdx.x];
+    FinalArgs a;
+    a.u_base = b.u + in.u;
+    a.du0 = b.du0 + in.u;
+    a.x0 = b.x0 + in.x0;
+    a.goal = b.goal + in.goal;
+    a.traj = b.traj + in.traj;
+    a.stats = b.stats + 6 * (size_t)blockIdx.x;
+    a.status = b.status + blockIdx.x;
+    a.n = in.n;
+    a.T = in.T;
+    for (int d = 0; d < 3; ++d) {
+        a.ulo[d] = in.ulo[d];
+        a.uhi[d] = in.uhi[d];
+    }
+    a.sc = in.sc;
+    a.thr2 = in.thr2;
+    a.safe2 = in.safe2;
+    a.goal_tol = in.goal_tol;
+    a.w_safe = in.w_safe;
+    a.d0_floor = in.d0_floor;
+    a.flags = b.flags;
+    switch (in.dyn) {
+        case HOLO2D: apply_final_body<HOLO2D>(a); break;
+        case HOLO3D: apply_final_body<HOLO3D>(a); break;
+        default: apply_final_body<UNICYCLE>(a); break;
+    }
+}
+
+static __global__ void k_fill_int(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 }  // namespace d4

@@ -1,0 +1,57 @@
+"""Batched form: uneven instances advanced together must reproduce each
+instance's single-problem iteration bit for bit, and their final rewards must
+match the oracle's reward of the same plans."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mbd as ombd
+from paper_2503_12204_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    assert torch.cuda.is_available(), "the GPU tests need a HIP device"
+    from paper_2503_12204_amd import _lib
+    return _lib
+
+
+def _mix(count, M, N, seed=0, n_range=(2, 32), t_range=(9, 61)):
+    out = W.batched_mix(count=count, n_samples=M, n_range=n_range, t_range=t_range, seed=seed)
+    return [(p.replace(n_steps=N), x0, g) for p, x0, g in out]
+
+
+def test_batch_equals_single_problem_runs(L):
+    inst = _mix(7, 160, 12, seed=3)
+    inst.append(W.holo3d_sphere(n=32, horizon=20, n_samples=160))
+    inst[-1] = (inst[-1][0].replace(n_steps=12, instance_id=7), inst[-1][1], inst[-1][2])
+    probs = [p for p, _, _ in inst]
+    print("shapes", [(p.dyn, p.n_robots, p.horizon) for p in probs], flush=True)
+    bc = L.BatchContext(probs, [x for _, x, _ in inst], [g for _, _, g in inst])
+    rng = np.random.default_rng(1)
+    plans = [rng.uniform(-0.5, 0.5, size=(p.n_robots, p.horizon, p.du)).astype(np.float32) for p in probs]
+    bc.set_plans(plans)
+    for it in range(2):
+        stats = bc.iterate(it)
+    got = [bc.plan_of(j).cpu().numpy() for j in range(len(probs))]
+    bc.close()
+    for j, (p, x0, g) in enumerate(inst):
+        ctx = L.Context(p)
+        u = torch.as_tensor(plans[j], device="cuda").clone()
+        for it in range(2):
+            st = ctx.denoise_iter(torch.as_tensor(x0, device="cuda"), torch.as_tensor(g, device="cuda"), u, it)
+        ctx.close()
+        assert np.array_equal(u.cpu().numpy(), got[j]), f"instance {j}"
+        assert st == stats[j], f"instance {j}"
+        fin = ombd.apply_deformation(p, x0, g, got[j], np.zeros(p.D))
+        assert abs(stats[j]["reward"] - fin["r"]) <= 1e-3 * abs(fin["r"])
+        assert stats[j]["hits"] == fin["hits"]
+
+
+def test_batch_rejects_mixed_sampler_settings(L):
+    inst = _mix(2, 64, 5)
+    probs = [inst[0][0], inst[1][0].replace(temperature=0.2)]
+    with pytest.raises(L.D4Error):
+        L.BatchContext(probs, [x for _, x, _ in inst], [g for _, _, g in inst])
