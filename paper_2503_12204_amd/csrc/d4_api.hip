@@ -22,13 +22,14 @@ namespace {
 using namespace d4host;
 
 template <int DYN>
-void launch_rollfit_dyn(int mode, dim3 grid, dim3 block, size_t lds, hipStream_t st, const RollFitArgs& a) {
-    if (mode == MODE_ALIGNED) {
-        allow_lds(k_rollfit<DYN, MODE_ALIGNED>, lds);
-        hipLaunchKernelGGL((k_rollfit<DYN, MODE_ALIGNED>), grid, block, lds, st, a);
-    } else if (mode == MODE_STREAM) {
-        allow_lds(k_rollfit<DYN, MODE_STREAM>, lds);
-        hipLaunchKernelGGL((k_rollfit<DYN, MODE_STREAM>), grid, block, lds, st, a);
+void launch_rollfit_dyn(bool from_x, bool aligned, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                        const RollFitArgs& a) {
+    if (!from_x && aligned) {
+        allow_lds(k_rollfit<DYN, MODE_FUSED_ALIGNED>, lds);
+        hipLaunchKernelGGL((k_rollfit<DYN, MODE_FUSED_ALIGNED>), grid, block, lds, st, a);
+    } else if (!from_x) {
+        allow_lds(k_rollfit<DYN, MODE_FUSED>, lds);
+        hipLaunchKernelGGL((k_rollfit<DYN, MODE_FUSED>), grid, block, lds, st, a);
     } else {
         allow_lds(k_rollfit<DYN, MODE_FROM_X>, lds);
         hipLaunchKernelGGL((k_rollfit<DYN, MODE_FROM_X>), grid, block, lds, st, a);
@@ -41,11 +42,11 @@ int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStre
     const dim3 block(tile.S * p->n_robots);
     const size_t lds = rollfit_lds(p, tile);
     if (lds > 160 * 1024) return fail(D4_EUNSUPPORTED, "reward kernel needs %zu bytes of LDS", lds);
-    const int mode = FROM_X ? MODE_FROM_X : (aligned_ok(p, tile) ? MODE_ALIGNED : MODE_STREAM);
+    const bool al = draws_aligned(p) && !std::getenv("D4_NO_ALIGNED");
     switch (p->dyn) {
-        case HOLO2D: launch_rollfit_dyn<HOLO2D>(mode, grid, block, lds, st, a); break;
-        case HOLO3D: launch_rollfit_dyn<HOLO3D>(mode, grid, block, lds, st, a); break;
-        default: launch_rollfit_dyn<UNICYCLE>(mode, grid, block, lds, st, a); break;
+        case HOLO2D: launch_rollfit_dyn<HOLO2D>(FROM_X, al, grid, block, lds, st, a); break;
+        case HOLO3D: launch_rollfit_dyn<HOLO3D>(FROM_X, al, grid, block, lds, st, a); break;
+        default: launch_rollfit_dyn<UNICYCLE>(FROM_X, al, grid, block, lds, st, a); break;
     }
     HIP_LAUNCH_CHECK("k_rollfit");
     return D4_OK;

@@ -158,7 +158,7 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
         in.dyn = p.dyn;
         in.S = t.S;
         in.Tb = t.Tb;
-        in.mode = aligned_ok(&p, t) ? MODE_ALIGNED : MODE_STREAM;
+        in.mode = draws_aligned(&p) ? MODE_FUSED_ALIGNED : MODE_FUSED;
         in.D = p.n_robots * p.horizon * s.du;
         in.P = (int)((M + t.S - 1) / t.S);
         in.x0 = ox;

@@ -129,34 +129,6 @@ __device__ __forceinline__ void normal_block(uint32_t group, uint32_t m, uint32_
     box_muller(w2, w3, z2, z3);
 }
 
-// Streams the normals of consecutive elements e of one sample; a block is
-// generated when the element index crosses into it.
-struct NormalStream {
-    uint32_t group;
-    float z0, z1, z2, z3;
-    uint32_t m, c2, c3, k0, k1;
-
-    __device__ __forceinline__ void init(uint32_t m_, uint32_t c2_, uint32_t c3_, uint32_t k0_,
-                                         uint32_t k1_) {
-        group = 0xFFFFFFFFu;
-        z0 = z1 = z2 = z3 = 0.0f;
-        m = m_;
-        c2 = c2_;
-        c3 = c3_;
-        k0 = k0_;
-        k1 = k1_;
-    }
-    __device__ __forceinline__ float get(uint32_t e) {
-        const uint32_t g = e >> 2;
-        if (g != group) {
-            group = g;
-            normal_block(g, m, c2, c3, k0, k1, z0, z1, z2, z3);
-        }
-        const uint32_t j = e & 3u;
-        return j == 0 ? z0 : j == 1 ? z1 : j == 2 ? z2 : z3;
-    }
-};
-
 // Square root outside the bit-exact recipe (goal distances): one hardware
 // v_sqrt_f32 (1 ulp) instead of the correctly rounded sequence.
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }

@@ -188,13 +188,8 @@ inline size_t rollfit_lds(const d4_problem* p, Tile t) {
     return a > b ? a : b;
 }
 
-// Steps per noise chunk of the aligned fused kernel (whole Philox blocks).
-inline int chunk_steps(int du) { return du == 2 ? 2 : 4; }
-
-inline bool aligned_ok(const d4_problem* p, Tile t) {
-    const int du = shape_of(p->dyn).du;
-    return ((p->horizon * du) % 4 == 0) && (t.Tb % chunk_steps(du) == 0) && !std::getenv("D4_NO_ALIGNED");
-}
+// Whether every robot's draws start on a Philox block boundary.
+inline bool draws_aligned(const d4_problem* p) { return (p->horizon * shape_of(p->dyn).du) % 4 == 0; }
 
 inline RollFitArgs base_args(const d4_problem* p, Tile tile) {
     RollFitArgs a;

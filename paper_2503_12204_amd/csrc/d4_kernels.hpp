@@ -82,7 +82,9 @@ struct PosSlot<3> {
     }
 };
 
-enum { MODE_STREAM = 0, MODE_ALIGNED = 1, MODE_FROM_X = 2 };
+// MODE_FUSED_ALIGNED: every robot's first draw element is a multiple of 4
+// (T * d_u % 4 == 0), so the draw window needs no phase selection.
+enum { MODE_FUSED = 1, MODE_FROM_X = 2, MODE_FUSED_ALIGNED = 3 };
 
 // Steps per noise chunk (a whole number of Philox blocks) and blocks per chunk.
 template <int DU>
@@ -92,8 +94,8 @@ struct Chunk {
 };
 
 // Reward of one (sample, robot) lane per step block; see the mapping notes above.
-// MODE_ALIGNED requires T * d_u % 4 == 0 and Tb a multiple of Chunk::STEPS so
-// that every chunk of a robot's elements starts on a Philox block boundary.
+// MODE_FUSED draws, samples and rolls out; it requires Tb to be a multiple of
+// Chunk::STEPS.  MODE_FROM_X reads trajectories instead.
 // One tile: samples m0 .. m0+S-1 of one problem, lanes tid < n*S (the rest of
 // the workgroup idles through the barriers).  Writes the tile's reward
 // statistics to partials[part] when partials is set.
@@ -138,8 +140,11 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
 
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
     const uint32_t c2 = (iter << 16) | a.step;
-    NormalStream ns;
-    ns.init((uint32_t)mc, c2, a.inst, a.key0, a.key1);
+    // this robot's first draw element and its phase within a Philox block
+    const uint32_t ebase = (uint32_t)(k * T * DU);
+    const uint32_t phase = MODE == MODE_FUSED_ALIGNED ? 0u : (ebase & 3u);
+    float left[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (!FROM_X) normal_block(ebase >> 2, (uint32_t)mc, c2, a.inst, a.key0, a.key1, left[0], left[1], left[2], left[3]);
     float ulo[DU], uhi[DU];
 #pragma unroll
     for (int d = 0; d < DU; ++d) {
@@ -165,53 +170,55 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
         const int buf = b & 1;
         const int t0 = b * Tb;
         const int tcount = min(Tb, T - t0);
-        if (MODE == MODE_ALIGNED) {
+        if (!FROM_X) {
+            // Chunks of CS steps use CS*DU = 4*CG consecutive draws starting at
+            // phase p of a Philox block; the window holds the block the
+            // previous chunk ended in ("left") plus CG new blocks.
             constexpr int CS = Chunk<DU>::STEPS, CG = Chunk<DU>::GROUPS;
             for (int tc = 0; tc < tcount; tc += CS) {
                 const int t = t0 + tc;
-                const uint32_t e0 = (uint32_t)((k * T + t) * DU);
-                float z[4 * CG];
+                const uint32_t e0 = ebase + (uint32_t)(t * DU);
+                const uint32_t g0 = e0 >> 2;
+                float win[4 + 4 * CG];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) win[j] = left[j];
 #pragma unroll
                 for (int q = 0; q < CG; ++q)
-                    normal_block((e0 >> 2) + q, (uint32_t)mc, c2, a.inst, a.key0, a.key1, z[4 * q],
-                                 z[4 * q + 1], z[4 * q + 2], z[4 * q + 3]);
+                    normal_block(g0 + 1 + q, (uint32_t)mc, c2, a.inst, a.key0, a.key1, win[4 + 4 * q],
+                                 win[5 + 4 * q], win[6 + 4 * q], win[7 + 4 * q]);
+                float z[4 * CG];
+#pragma unroll
+                for (int j = 0; j < 4 * CG; ++j)
+                    z[j] = phase == 0 ? win[j] : phase == 1 ? win[j + 1] : phase == 2 ? win[j + 2] : win[j + 3];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) left[j] = win[4 * CG + j];
+                const int steps = min(CS, T - t);
                 if (live) {
 #pragma unroll
-                    for (int j = 0; j < 4 * CG; ++j) a.eps[(size_t)(e0 + j) * Ms + m] = z[j];
+                    for (int j = 0; j < 4 * CG; ++j)
+                        if (j < steps * DU) a.eps[(size_t)(e0 + j) * Ms + m] = z[j];
                 }
 #pragma unroll
                 for (int s = 0; s < CS; ++s) {
-                    float u[DU];
+                    if (s < steps) {
+                        float u[DU];
 #pragma unroll
-                    for (int d = 0; d < DU; ++d) {
-                        const uint32_t e = e0 + s * DU + d;
-                        const float cb = a.u_base[e] + a.du_in[e] * mscale;
-                        u[d] = fminf(fmaxf(cb + sigma * z[s * DU + d], ulo[d]), uhi[d]);
+                        for (int d = 0; d < DU; ++d) {
+                            const uint32_t e = e0 + s * DU + d;
+                            const float cb = a.u_base[e] + a.du_in[e] * mscale;
+                            u[d] = fminf(fmaxf(cb + sigma * z[s * DU + d], ulo[d]), uhi[d]);
+                        }
+                        DY::step(x, aux, u, a.sc);
+                        after_step(buf, tc + s);
                     }
-                    DY::step(x, aux, u, a.sc);
-                    after_step(buf, tc + s);
                 }
             }
         } else {
             for (int tt = 0; tt < tcount; ++tt) {
                 const int t = t0 + tt;
-                if (FROM_X) {
-                    const float* xr = a.xs + (((size_t)mc * n + k) * (size_t)(T + 1) + (t + 1)) * DX;
+                const float* xr = a.xs + (((size_t)mc * n + k) * (size_t)(T + 1) + (t + 1)) * DX;
 #pragma unroll
-                    for (int c = 0; c < DP; ++c) x[c] = xr[c];
-                } else {
-                    float u[DU];
-                    const uint32_t e0 = (uint32_t)((k * T + t) * DU);
-#pragma unroll
-                    for (int d = 0; d < DU; ++d) {
-                        const uint32_t e = e0 + d;
-                        const float z = ns.get(e);
-                        if (live) a.eps[(size_t)e * Ms + m] = z;
-                        const float cb = a.u_base[e] + a.du_in[e] * mscale;
-                        u[d] = fminf(fmaxf(cb + sigma * z, ulo[d]), uhi[d]);
-                    }
-                    DY::step(x, aux, u, a.sc);
-                }
+                for (int c = 0; c < DP; ++c) x[c] = xr[c];
                 after_step(buf, tt);
             }
         }
@@ -662,19 +669,19 @@ static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArg
     a.iter = 0;
     a.inst = in.inst_id;
     a.flags = b.flags;
-    const bool al = in.mode == MODE_ALIGNED;
+    const bool al = in.mode == MODE_FUSED_ALIGNED;
     switch (in.dyn) {
         case HOLO2D:
-            if (al) rollfit_tile<HOLO2D, MODE_ALIGNED>(a, tl.m0, tl.part, lds);
-            else rollfit_tile<HOLO2D, MODE_STREAM>(a, tl.m0, tl.part, lds);
+            if (al) rollfit_tile<HOLO2D, MODE_FUSED_ALIGNED>(a, tl.m0, tl.part, lds);
+            else rollfit_tile<HOLO2D, MODE_FUSED>(a, tl.m0, tl.part, lds);
             break;
         case HOLO3D:
-            if (al) rollfit_tile<HOLO3D, MODE_ALIGNED>(a, tl.m0, tl.part, lds);
-            else rollfit_tile<HOLO3D, MODE_STREAM>(a, tl.m0, tl.part, lds);
+            if (al) rollfit_tile<HOLO3D, MODE_FUSED_ALIGNED>(a, tl.m0, tl.part, lds);
+            else rollfit_tile<HOLO3D, MODE_FUSED>(a, tl.m0, tl.part, lds);
             break;
         default:
-            if (al) rollfit_tile<UNICYCLE, MODE_ALIGNED>(a, tl.m0, tl.part, lds);
-            else rollfit_tile<UNICYCLE, MODE_STREAM>(a, tl.m0, tl.part, lds);
+            if (al) rollfit_tile<UNICYCLE, MODE_FUSED_ALIGNED>(a, tl.m0, tl.part, lds);
+            else rollfit_tile<UNICYCLE, MODE_FUSED>(a, tl.m0, tl.part, lds);
             break;
     }
 }

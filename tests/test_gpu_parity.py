@@ -302,9 +302,9 @@ def test_invalid_arguments_raise(L):
         L.Context(p.replace(temperature=0.0))
 
 
-def test_aligned_and_streamed_noise_paths_agree(L):
-    """The whole-block (aligned) and per-element (streamed) draw paths of the
-    fused kernel produce the same draws and the same rewards."""
+def test_phase_free_and_general_draw_windows_agree(L):
+    """The phase-0 draw window (T d_u a multiple of 4) and the general window
+    produce the same draws, rewards and counts."""
     p, x0, g = W.holo3d_sphere(n=8, horizon=40, n_samples=256)
     rng = np.random.default_rng(2)
     ub = _cu(_rand_controls(rng, p, 1, spread=0.5)[0].reshape(-1))
