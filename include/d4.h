@@ -201,6 +201,63 @@ int32_t d4_batch_iter(d4_batch* batch, const float* x0_all, const float* goal_al
 
 int32_t d4_batch_destroy(d4_batch* batch);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal: a permutation-equivariant set network that predicts the
+ * initial plan tau.u from which Algorithm 2 starts (the paper initialises tau
+ * without learning; the planner still judges and refines the prediction).
+ * Per robot r of instance b:
+ *   h_0 = x_r W_e + b_e
+ *   h_{l+1} = h_l + relu(h_l W1_l + b1_l) W2_l + b2_l + mean_{r' in b}(h_l,r') Wp_l
+ *   y_r = h_L W_h + b_h            (y_r: the robot's T*d_u controls)
+ * Weights are FP32 master copies rounded to BF16 for every product; products
+ * run on the BF16 MFMA with FP32 accumulation.  Loss: sum_r mask_r
+ * |y_r - t_r|^2 / (2 d_out sum_r mask_r); optimiser Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8) with bias correction.  Flat parameter order: W_e [d_in][W],
+ * b_e [W], then per layer W1 [W][H], b1 [H], W2 [H][W], b2 [W], Wp [W][W],
+ * then W_h [W][d_out], b_h [d_out] (row-major).
+ * ------------------------------------------------------------------------ */
+typedef struct d4p_config {
+    int32_t d_in;       /* per-robot features */
+    int32_t width;      /* W */
+    int32_t hidden;     /* H */
+    int32_t layers;     /* L */
+    int32_t d_out;      /* T * d_u */
+    int32_t max_rows;   /* most robots in one call (sum over instances) */
+    int32_t max_batch;  /* most instances in one call */
+    uint64_t seed;      /* initialisation: uniform(+-1/sqrt(fan_in)) weights, zero biases */
+} d4p_config;
+
+typedef struct d4p_net d4p_net;
+
+int32_t d4p_create(const d4p_config* cfg, d4p_net** net);
+int32_t d4p_destroy(d4p_net* net);
+int32_t d4p_num_params(const d4p_net* net, int64_t* count);       /* count: host */
+/* params: device [count] FP32 in the flat order above; set also resets Adam. */
+int32_t d4p_set_params(d4p_net* net, const float* params, void* stream);
+int32_t d4p_get_params(const d4p_net* net, float* params, void* stream);
+
+/* x [rows][d_in] features, seg [batch+1] device int32 row offsets of the
+ * instances (seg[0] = 0, seg[batch] = rows, every instance non-empty);
+ * writes y [rows][d_out]. */
+int32_t d4p_forward(d4p_net* net, const float* x, const int32_t* seg, int32_t rows, int32_t batch, float* y,
+                    void* stream);
+
+/* Forward and backward: loss (device [1]) and grads (device [count], flat
+ * order) unless NULL.  target [rows][d_out], mask [rows] (0 or 1). */
+int32_t d4p_gradients(d4p_net* net, const float* x, const int32_t* seg, int32_t rows, int32_t batch,
+                      const float* target, const float* mask, float* loss, float* grads, void* stream);
+
+/* d4p_gradients followed by one Adam step with learning rate lr > 0. */
+int32_t d4p_train_step(d4p_net* net, const float* x, const int32_t* seg, int32_t rows, int32_t batch,
+                       const float* target, const float* mask, float lr, float* loss, void* stream);
+
+/* The network's product kernel on its own: C[M][N] = op(A) op(B) + beta C,
+ * A and B BF16 (bit patterns in uint16), C FP32 row-major; op(A) = A [M][K]
+ * (lda >= K) or, with trans_a, A^T for A stored [K][M] (lda >= M); likewise
+ * op(B) = B [K][N] or B^T for B stored [N][K]. */
+int32_t d4p_gemm_bf16(int32_t trans_a, int32_t trans_b, const uint16_t* A, const uint16_t* B, float* C, int32_t M,
+                      int32_t N, int32_t K, int32_t lda, int32_t ldb, int32_t ldc, float beta, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

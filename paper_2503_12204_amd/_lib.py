@@ -307,3 +307,102 @@ class BatchContext:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ learned proposal
+class D4PConfig(ctypes.Structure):
+    _fields_ = [("d_in", c_int32), ("width", c_int32), ("hidden", c_int32), ("layers", c_int32),
+                ("d_out", c_int32), ("max_rows", c_int32), ("max_batch", c_int32), ("seed", c_uint64)]
+
+
+def _load_proposal():
+    fp = c_void_p
+    sig = {
+        "d4p_create": ([POINTER(D4PConfig), POINTER(c_void_p)], c_int32),
+        "d4p_destroy": ([c_void_p], c_int32),
+        "d4p_num_params": ([c_void_p, POINTER(ctypes.c_int64)], c_int32),
+        "d4p_set_params": ([c_void_p, fp, c_void_p], c_int32),
+        "d4p_get_params": ([c_void_p, fp, c_void_p], c_int32),
+        "d4p_forward": ([c_void_p, fp, fp, c_int32, c_int32, fp, c_void_p], c_int32),
+        "d4p_gradients": ([c_void_p, fp, fp, c_int32, c_int32, fp, fp, fp, fp, c_void_p], c_int32),
+        "d4p_train_step": ([c_void_p, fp, fp, c_int32, c_int32, fp, fp, c_float, fp, c_void_p], c_int32),
+        "d4p_gemm_bf16": ([c_int32, c_int32, fp, fp, fp, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32,
+                           c_float, c_void_p], c_int32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(_lib, name)
+        fn.argtypes = args
+        fn.restype = res
+
+
+_load_proposal()
+
+
+def gemm_bf16(A, B, M, N, K, trans_a=False, trans_b=False, C=None, beta=0.0):
+    """C[M][N] (+)= op(A) op(B) on the BF16 MFMA kernel; A, B bfloat16 CUDA tensors."""
+    if C is None:
+        C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+    lda = M if trans_a else K
+    ldb = K if trans_b else N
+    _check(_lib.d4p_gemm_bf16(int(trans_a), int(trans_b), _dev(A, dtype=torch.bfloat16, name="A"),
+                              _dev(B, dtype=torch.bfloat16, name="B"), _dev(C, name="C"), M, N, K, lda, ldb, N,
+                              float(beta), _stream()))
+    return C
+
+
+class ProposalNet:
+    """The set network of d4p_* (weights, Adam state and workspace on the GPU)."""
+
+    def __init__(self, d_in=6, width=256, hidden=512, layers=4, d_out=200, max_rows=4096, max_batch=512, seed=0):
+        self.cfg = D4PConfig(d_in, width, hidden, layers, d_out, max_rows, max_batch, seed)
+        h = c_void_p()
+        _check(_lib.d4p_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64()
+        _check(_lib.d4p_num_params(h, ctypes.byref(n)))
+        self.n_params = int(n.value)
+        self._loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def set_params(self, flat):
+        flat = _f32(flat)
+        _check(_lib.d4p_set_params(self._h, _dev(flat, (self.n_params,), name="params"), _stream()))
+
+    def get_params(self):
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(_lib.d4p_get_params(self._h, _dev(out), _stream()))
+        return out
+
+    def forward(self, x, seg):
+        R, B = x.shape[0], seg.shape[0] - 1
+        y = torch.empty((R, self.cfg.d_out), dtype=torch.float32, device="cuda")
+        _check(_lib.d4p_forward(self._h, _dev(x, (R, self.cfg.d_in), name="x"),
+                                _dev(seg, dtype=torch.int32, name="seg"), R, B, _dev(y), _stream()))
+        return y
+
+    def gradients(self, x, seg, target, mask):
+        R, B = x.shape[0], seg.shape[0] - 1
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(_lib.d4p_gradients(self._h, _dev(x, (R, self.cfg.d_in), name="x"),
+                                  _dev(seg, dtype=torch.int32, name="seg"), R, B,
+                                  _dev(target, (R, self.cfg.d_out), name="target"), _dev(mask, (R,), name="mask"),
+                                  _dev(self._loss), _dev(g), _stream()))
+        return self._loss.clone(), g
+
+    def train_step(self, x, seg, target, mask, lr):
+        R, B = x.shape[0], seg.shape[0] - 1
+        _check(_lib.d4p_train_step(self._h, _dev(x, (R, self.cfg.d_in), name="x"),
+                                   _dev(seg, dtype=torch.int32, name="seg"), R, B,
+                                   _dev(target, (R, self.cfg.d_out), name="target"),
+                                   _dev(mask, (R,), name="mask"), float(lr), _dev(self._loss), _stream()))
+        return self._loss
+
+    def close(self):
+        if self._h:
+            _lib.d4p_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

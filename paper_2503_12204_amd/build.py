@@ -13,8 +13,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libd4.so")
 
-SOURCES = ["d4_api.hip", "d4_batch.hip"]
-HEADERS = ["d4_device.hpp", "d4_kernels.hpp", "d4_host.hpp"]
+SOURCES = ["d4_api.hip", "d4_batch.hip", "d4_proposal.hip"]
+HEADERS = ["d4_device.hpp", "d4_kernels.hpp", "d4_host.hpp", "d4_proposal_kernels.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,283 @@
+// Kernels of the learned proposal: a permutation-equivariant set network over
+// the robots of each instance, trained on plans the planner solved.
+//
+//  k_gemm_bf16<TA,TB>  C = alpha op(A) op(B) + beta C with BF16 operands and FP32
+//                      accumulation on the 32x32x16 MFMA; op(X) = X or X^T.
+//                      64x64 workgroup tiles, four waves of 32x32, K steps of 32
+//                      staged in LDS k-contiguous for both operands.
+//  elementwise         embedding, bias + ReLU, instance mean / sum pooling and
+//                      their broadcasts, residual sums, masked MSE, column sums,
+//                      Adam with FP32 master weights, BF16 rounding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace d4p {
+
+typedef uint16_t bf16_t;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ bf16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr int BM = 64, BN = 64, BK = 32, KPAD = 8;
+
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm_bf16(const bf16_t* __restrict__ A, const bf16_t* __restrict__ B,
+                                                   float* __restrict__ C, int M, int N, int K, int lda,
+                                                   int ldb, int ldc, float alpha, float beta) {
+    __shared__ __attribute__((aligned(16))) bf16_t As[BM][BK + KPAD];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[BN][BK + KPAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        // A tile -> As[m][k]
+        if (!TA) {
+            const int row = tid >> 2, kk = (tid & 3) * 8;
+            const int gm = m0 + row;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int gk = k0 + kk + i;
+                As[row][kk + i] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : (bf16_t)0;
+            }
+        } else {
+            const int kk = tid >> 3, mm = (tid & 7) * 8;
+            const int gk = k0 + kk;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int gm = m0 + mm + i;
+                As[mm + i][kk] = (gm < M && gk < K) ? A[(size_t)gk * lda + gm] : (bf16_t)0;
+            }
+        }
+        // B tile -> Bs[n][k]
+        if (TB) {
+            const int row = tid >> 2, kk = (tid & 3) * 8;
+            const int gn = n0 + row;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int gk = k0 + kk + i;
+                Bs[row][kk + i] = (gn < N && gk < K) ? B[(size_t)gn * ldb + gk] : (bf16_t)0;
+            }
+        } else {
+            const int kk = tid >> 3, nn = (tid & 7) * 8;
+            const int gk = k0 + kk;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int gn = n0 + nn + i;
+                Bs[nn + i][kk] = (gn < N && gk < K) ? B[(size_t)gk * ldb + gn] : (bf16_t)0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < BK; kb += 16) {
+            const int r = lane & 31, kq = kb + (lane >> 5) * 8;
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + r][kq]);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + r][kq]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // lane l holds column l%32, rows 8*(v/4) + 4*(l/32) + v%4 of the wave's 32x32 block
+    const int col = n0 + wn * 32 + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        if (row < M && col < N) {
+            float* c = C + (size_t)row * ldc + col;
+            *c = beta == 0.0f ? alpha * acc[v] : alpha * acc[v] + beta * *c;
+        }
+    }
+}
+
+__global__ void k_cast_bf16(const float* __restrict__ x, bf16_t* __restrict__ y, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = to_bf16(x[i]);
+}
+
+// instance index of every row from offsets seg[B+1]
+__global__ void k_row_inst(const int* __restrict__ seg, int B, int* __restrict__ inst) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B)
+        for (int r = seg[b]; r < seg[b + 1]; ++r) inst[r] = b;
+}
+
+// h = x W_e + b_e with W_e in BF16 (K = d_in is small: plain FMA)
+__global__ void k_embed(const float* __restrict__ x, const bf16_t* __restrict__ We, const float* __restrict__ be,
+                        float* __restrict__ h, bf16_t* __restrict__ hb, int R, int d_in, int W) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)R * W) return;
+    const int r = (int)(i / W), c = (int)(i - (long long)r * W);
+    float acc = be[c];
+    for (int j = 0; j < d_in; ++j) acc += x[(size_t)r * d_in + j] * from_bf16(We[(size_t)j * W + c]);
+    h[i] = acc;
+    hb[i] = to_bf16(acc);
+}
+
+// z += b (in place), a = bf16(relu(z))
+__global__ void k_bias_relu(float* __restrict__ z, const float* __restrict__ b, bf16_t* __restrict__ a, int R, int H) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)R * H) return;
+    const int c = (int)(i % H);
+    const float v = z[i] + b[c];
+    z[i] = v;
+    a[i] = to_bf16(fmaxf(v, 0.0f));
+}
+
+// per-instance mean (mean = true) or sum of rows; one thread per (instance, column)
+__global__ void k_segment_reduce(const float* __restrict__ x, const int* __restrict__ seg, float* __restrict__ out,
+                                 bf16_t* __restrict__ outb, int B, int W, int mean) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)B * W) return;
+    const int b = (int)(i / W), c = (int)(i - (long long)b * W);
+    const int r0 = seg[b], r1 = seg[b + 1];
+    float s = 0.0f;
+    for (int r = r0; r < r1; ++r) s += x[(size_t)r * W + c];
+    if (mean) s /= (float)max(r1 - r0, 1);
+    if (out) out[i] = s;
+    outb[i] = to_bf16(s);
+}
+
+// h_next = h + z2 + b2 + q[inst]
+__global__ void k_residual(const float* __restrict__ h, const float* __restrict__ z2, const float* __restrict__ b2,
+                           const float* __restrict__ q, const int* __restrict__ inst, float* __restrict__ hn,
+                           bf16_t* __restrict__ hnb, int R, int W) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)R * W) return;
+    const int r = (int)(i / W), c = (int)(i - (long long)r * W);
+    const float v = h[i] + z2[i] + b2[c] + q[(size_t)inst[r] * W + c];
+    hn[i] = v;
+    hnb[i] = to_bf16(v);
+}
+
+__global__ void k_add_bias(float* __restrict__ y, const float* __restrict__ b, int R, int N) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (long long)R * N) y[i] += b[i % N];
+}
+
+// dy = mask (y - t) / (N sum(mask)); per-block partial loss sums (FP32)
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const float* __restrict__ t,
+                                             const float* __restrict__ mask, const float* __restrict__ msum,
+                                             float* __restrict__ dy, bf16_t* __restrict__ dyb,
+                                             float* __restrict__ partial, int R, int N) {
+    __shared__ float red[256];
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (i < (long long)R * N) {
+        const int r = (int)(i / N);
+        const float cnt = (float)N * fmaxf(*msum, 1.0f);
+        const float d = (y[i] - t[i]) * mask[r];
+        l = d * (y[i] - t[i]);
+        const float g = d / cnt;
+        dy[i] = g;
+        dyb[i] = to_bf16(g);
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ partial, int n, float scale,
+                                                      float* __restrict__ out) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
+// loss = sum(partial) / (2 N sum(mask))
+__global__ void __launch_bounds__(256) k_loss_final(const float* __restrict__ partial, int n, int N,
+                                                    const float* __restrict__ msum, float* __restrict__ out) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] / (2.0f * (float)N * fmaxf(*msum, 1.0f));
+}
+
+// out[c] = sum_r x[r][c]; one thread per column
+__global__ void k_colsum(const float* __restrict__ x, float* __restrict__ out, int R, int N) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    float s = 0.0f;
+    for (int r = 0; r < R; ++r) s += x[(size_t)r * N + c];
+    out[c] = s;
+}
+
+// dz = da * (z > 0), in place on da, plus its BF16 copy
+__global__ void k_relu_bwd(float* __restrict__ da, const float* __restrict__ z, bf16_t* __restrict__ dzb, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = z[i] > 0.0f ? da[i] : 0.0f;
+    da[i] = v;
+    dzb[i] = to_bf16(v);
+}
+
+// dh[r] += dpm[inst r] / n_inst
+__global__ void k_pool_bwd(float* __restrict__ dh, const float* __restrict__ dpm, const int* __restrict__ inst,
+                           const int* __restrict__ seg, int R, int W) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)R * W) return;
+    const int r = (int)(i / W), c = (int)(i - (long long)r * W);
+    const int b = inst[r];
+    dh[i] += dpm[(size_t)b * W + c] / (float)(seg[b + 1] - seg[b]);
+}
+
+// gWe[j][c] = sum_r x[r][j] dh[r][c]
+__global__ void k_embed_grad(const float* __restrict__ x, const float* __restrict__ dh, float* __restrict__ g,
+                             int R, int d_in, int W) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d_in * W) return;
+    const int j = i / W, c = i - j * W;
+    float s = 0.0f;
+    for (int r = 0; r < R; ++r) s += x[(size_t)r * d_in + j] * dh[(size_t)r * W + c];
+    g[i] = s;
+}
+
+// Adam with bias correction on FP32 master weights, then their BF16 copy
+__global__ void k_adam(float* __restrict__ w, bf16_t* __restrict__ wb, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, long long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = to_bf16(wi);
+}
+
+__global__ void k_zero(float* __restrict__ p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+}  // namespace d4p
