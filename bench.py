@@ -161,6 +161,11 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="only launch the fused kernel this many times (for counter runs)")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--experiment", choices=["batched", "proposal"], default=None,
+                    help="time-to-target of the batched or learned-proposal form against the plain planner")
+    ap.add_argument("--train-teams", type=int, default=4096)
+    ap.add_argument("--test-teams", type=int, default=1000)
+    ap.add_argument("--epochs", type=int, default=20)
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -175,6 +180,30 @@ def main():
     from paper_2503_12204_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.experiment:
+        from paper_2503_12204_amd import experiments as E
+
+        def log(msg):
+            print(msg, file=sys.stderr, flush=True)
+
+        if args.experiment == "batched":
+            res = E.batched_vs_plain(L, log=log)
+            out = {"metric": "time-to-target speedup of the batched form over the plain planner",
+                   "value": res["speedup"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
+                   "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": "batched_mix", "description": "512 instances, robots U{2..32}, "
+                              "horizon U{40..160}, 3 dynamics, M=1024, N=100, random starts/goals in a 10 m box"},
+                   "details": res}
+        else:
+            res = E.proposal_gain(L, n_train=args.train_teams, n_test=args.test_teams, epochs=args.epochs, log=log)
+            out = {"metric": "time-to-target speedup of the learned proposal over the plain planner",
+                   "value": res["time_to_target_speedup"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
+                   "dtype": "f32 planner, bf16 network", "data": "synthetic",
+                   "config": {"workload": "learned_proposal", "description": "2D holonomic teams of 4..16 robots, "
+                              "random starts/goals in a 10 m box, T=100, N=100, evaluation at M=2048"},
+                   "details": res}
+        print(json.dumps(out), flush=True)
+        return
     p, x0n, gn = make_workload(args.workload)
     x0 = torch.as_tensor(x0n, device="cuda")
     g = torch.as_tensor(gn, device="cuda")

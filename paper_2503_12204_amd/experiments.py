@@ -1,0 +1,137 @@
+"""Time-to-target comparisons of the batched and learned-proposal forms
+against the plain planner on the same GPU.
+
+batched_vs_plain: many uneven instances, one batched iteration against the
+    same instances run one after another through the single-problem path
+    (identical results, so time-to-target is the time for the same work).
+proposal_gain: train the proposal on teams the planner solved, then run the
+    plain planner from zero controls and from the judged proposal on
+    held-out teams; an instance's target is the reward the plain planner
+    reaches with its full iteration budget.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import proposal as PR
+from . import workloads as W
+
+
+def batched_vs_plain(L, count=512, n_samples=1024, iterations=2, seed=0, log=print):
+    inst = W.batched_mix(count=count, n_samples=n_samples, seed=seed)
+    probs = [p for p, _, _ in inst]
+    units = sum(p.n_robots * p.horizon * p.n_samples * p.n_steps for p in probs)
+    bc = L.BatchContext(probs, [x for _, x, _ in inst], [g for _, _, g in inst])
+    bc.iterate(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(iterations):
+        bc.iterate(k + 1, sync=False)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / iterations
+    bc.close()
+    log(f"batched: {t_batch * 1e3:.1f} ms per iteration of {count} instances")
+    ctxs = []
+    for p, x0, g in inst:
+        ctxs.append((L.Context(p), torch.as_tensor(x0, device="cuda"), torch.as_tensor(g, device="cuda"),
+                     torch.zeros((p.n_robots, p.horizon, p.du), device="cuda")))
+    for c, x0, g, u in ctxs:
+        c.denoise_iter(x0, g, u, 0, sync=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(iterations):
+        for c, x0, g, u in ctxs:
+            c.denoise_iter(x0, g, u, k + 1, sync=False)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / iterations
+    for c, _, _, _ in ctxs:
+        c.close()
+    log(f"plain, one instance after another: {t_plain * 1e3:.1f} ms per iteration")
+    return {"instances": count, "samples": n_samples, "batched_ms_per_iteration": t_batch * 1e3,
+            "plain_sequential_ms_per_iteration": t_plain * 1e3, "speedup": t_plain / t_batch,
+            "batched_robot_step_samples_per_s": units / t_batch}
+
+
+def _chunks(seq, k):
+    for i in range(0, len(seq), k):
+        yield seq[i:i + k]
+
+
+def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=3, eval_samples=2048,
+                  eval_iters=5, epochs=20, seed=0, log=print):
+    rng = np.random.default_rng(1_000_000 + seed)
+    t0 = time.perf_counter()
+    train = [PR.random_team(rng, n_samples=label_samples, instance_id=j) for j in range(n_train)]
+    plans, rewards, success = [], [], []
+    for chunk in _chunks(train, 512):
+        pl, hist, _ = PR.run_planner(L, chunk, iterations=label_iters)
+        plans += pl
+        rewards += [s["reward"] for s in hist[-1]]
+        success += [s["success"] for s in hist[-1]]
+    rewards, success = np.array(rewards), np.array(success)
+    mask = success if success.mean() >= 0.25 else rewards >= np.median(rewards)
+    t_label = time.perf_counter() - t0
+    log(f"labelled {n_train} teams in {t_label:.1f} s: success {success.mean():.3f}, "
+        f"mean reward {rewards.mean():.4f}, training on {int(mask.sum())}")
+    prop = PR.Proposal(L, seed=seed)
+    t0 = time.perf_counter()
+    losses = prop.fit(train, plans, mask, epochs=epochs, batch=64, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained {epochs} epochs in {t_train:.1f} s, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+
+    trng = np.random.default_rng(seed)
+    test = [PR.random_team(trng, n_samples=eval_samples, instance_id=j) for j in range(n_test)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    init, used = prop.judged_initial_plans(test)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t0
+    r_init = np.array([PR.plan_reward(L, t, u) for t, u in zip(test, init)])
+    hp, hn, tp, tn = [], [], [], []
+    for c0 in range(0, n_test, 500):
+        ch = test[c0:c0 + 500]
+        _, h1, t1 = PR.run_planner(L, ch, iterations=eval_iters)
+        _, h2, t2 = PR.run_planner(L, ch, iterations=eval_iters, init_plans=init[c0:c0 + 500])
+        hp.append(h1)
+        hn.append(h2)
+        tp.append(t1)               # seconds per batched iteration of this chunk
+        tn.append(t2)
+    hist_p = [sum((h[k] for h in hp), []) for k in range(eval_iters)]
+    hist_n = [sum((h[k] for h in hn), []) for k in range(eval_iters)]
+    t_iter = sum(tp) / n_test       # seconds of batched iteration per team
+    target = np.array([s["reward"] for s in hist_p[-1]])
+    k_p = PR.iterations_to_target(hist_p, target)
+    k_n = PR.iterations_to_target(hist_n, target, init_rewards=r_init)
+    reach_n = k_n <= eval_iters
+    succ_p = PR.iterations_to_target([[{"reward": float(s["success"])} for s in it] for it in hist_p],
+                                     np.ones(n_test))
+    succ_n = PR.iterations_to_target([[{"reward": float(s["success"])} for s in it] for it in hist_n],
+                                     np.ones(n_test))
+    kp_mean = float(k_p.mean())
+    kn_eff = np.where(reach_n, k_n, eval_iters + 1)
+    kn_mean = float(kn_eff.mean())
+    t_plain = kp_mean * t_iter
+    t_net = kn_mean * t_iter + t_infer / n_test
+    out = {
+        "train_teams": n_train, "test_teams": n_test, "label_samples": label_samples, "label_iterations": label_iters,
+        "eval_samples": eval_samples, "eval_iterations": eval_iters, "epochs": epochs,
+        "label_seconds": t_label, "train_seconds": t_train, "final_loss": losses[-1],
+        "proposal_used_fraction": float(np.mean(used)),
+        "initial_reward_mean": {"zero": 0.0, "proposal": float(r_init.mean())},
+        "reward_after_iteration": {"plain": [float(np.mean([s["reward"] for s in it])) for it in hist_p],
+                                   "proposal": [float(np.mean([s["reward"] for s in it])) for it in hist_n]},
+        "success_after_iteration": {"plain": [float(np.mean([s["success"] for s in it])) for it in hist_p],
+                                    "proposal": [float(np.mean([s["success"] for s in it])) for it in hist_n]},
+        "iterations_to_target_mean": {"plain": kp_mean, "proposal": kn_mean},
+        "target_reached_fraction": {"plain": 1.0, "proposal": float(reach_n.mean())},
+        "iterations_to_first_success_mean": {"plain": float(succ_p.mean()), "proposal": float(succ_n.mean())},
+        "seconds_per_iteration_per_team": t_iter, "proposal_inference_seconds_per_team": t_infer / n_test,
+        "time_to_target_seconds_per_team": {"plain": t_plain, "proposal": t_net},
+        "time_to_target_speedup": t_plain / t_net,
+    }
+    prop.close()
+    return out
