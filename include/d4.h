@@ -168,6 +168,27 @@ int32_t d4_denoise_iter(d4_ctx* ctx, const d4_problem* p, const float* x0, const
                         void* stream);
 
 /* ------------------------------------------------------------------------
+ * Launch-shape tuning of the reward kernels (d4_sample_rollout_fitness,
+ * d4_fitness, d4_denoise_iter).  A tile is the number of samples per
+ * workgroup (1..64, times n_robots at most 1024 lanes) and the number of
+ * steps per LDS time block (a multiple of 2 for d_u = 2, of 4 for d_u = 3).
+ * The choice changes only speed and the grouping of the reward statistics
+ * (so results change in the last bits); the batched form keeps its own rule.
+ * ------------------------------------------------------------------------ */
+
+/* Install (or, with samples_per_group = 0, remove) a process-wide tile for
+ * problems of this (dyn, n_robots, horizon). */
+int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samples_per_group,
+                    int32_t steps_per_block);
+
+/* Time every admissible tile on the current device with the fused kernel of
+ * problem p (scratch buffers are allocated and freed here; synchronises the
+ * null stream), install the fastest and report it (outputs are host
+ * pointers, each may be NULL). */
+int32_t d4_autotune(const d4_problem* p, int32_t reps, int32_t* samples_per_group, int32_t* steps_per_block,
+                    float* best_us);
+
+/* ------------------------------------------------------------------------
  * Batched form: many independent problems advanced together.  Each instance
  * runs exactly the iteration of d4_denoise_iter (Algorithm 2 loop body over
  * Algorithm 1), with its own team size, horizon, dynamics, limits, start and

@@ -1,0 +1,91 @@
+"""Tile autotuning of the reward kernels with a JSON cache.
+
+A cache entry is keyed by the GPU architecture, a hash of the kernel
+sources, the dynamics, team size and horizon (and records the sample count it
+was tuned at).  `tune` runs d4_autotune for shapes not in the cache and
+installs the result; `install_cache` re-installs every cached tile of this
+architecture and source version in the current process.
+"""
+from __future__ import annotations
+
+import ctypes
+import hashlib
+import json
+import os
+
+import torch
+
+from . import _lib as L
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "d4orm_mi355x_tiles.json")
+
+L.lib().d4_tile_set.argtypes = [ctypes.c_int32] * 5
+L.lib().d4_tile_set.restype = ctypes.c_int32
+L.lib().d4_autotune.argtypes = [ctypes.POINTER(L.D4Problem), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
+L.lib().d4_autotune.restype = ctypes.c_int32
+
+
+def source_version():
+    h = hashlib.sha256()
+    for f in ("d4_device.hpp", "d4_kernels.hpp", "d4_host.hpp", "d4_api.hip"):
+        with open(os.path.join(_HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _arch():
+    return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+
+
+def _key(p):
+    return f"{_arch()}|{source_version()}|{p.dyn}|{p.n_robots}|{p.horizon}"
+
+
+def _load(path):
+    if os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def set_tile(dyn, n, horizon, samples_per_group, steps_per_block):
+    L._check(L.lib().d4_tile_set(dyn, n, horizon, samples_per_group, steps_per_block))
+
+
+def clear_tile(dyn, n, horizon):
+    L._check(L.lib().d4_tile_set(dyn, n, horizon, 0, 0))
+
+
+def tune(p, path=DEFAULT_CACHE, reps=5, force=False):
+    """Tile for problem p: from the cache, else measured now (and cached)."""
+    cache = _load(path)
+    key = _key(p)
+    if key in cache and not force:
+        e = cache[key]
+        set_tile(p.dyn, p.n_robots, p.horizon, e["S"], e["Tb"])
+        return e
+    S, Tb, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    c = L.to_c(p)
+    L._check(L.lib().d4_autotune(ctypes.byref(c), reps, ctypes.byref(S), ctypes.byref(Tb), ctypes.byref(us)))
+    e = {"S": S.value, "Tb": Tb.value, "us": us.value, "n_samples": p.n_samples}
+    cache[key] = e
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return e
+
+
+def install_cache(path=DEFAULT_CACHE):
+    """Install every cached tile of this architecture and source version; returns how many."""
+    prefix = f"{_arch()}|{source_version()}|"
+    k = 0
+    for key, e in _load(path).items():
+        if key.startswith(prefix):
+            dyn, n, T = (int(v) for v in key[len(prefix):].split("|"))
+            set_tile(dyn, n, T, e["S"], e["Tb"])
+            k += 1
+    return k

@@ -9,6 +9,9 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -442,6 +445,134 @@ int32_t d4_denoise_iter(d4_ctx* c, const d4_problem* p, const float* x0, const f
     if (traj_out)
         HIP_TRY(hipMemcpyAsync(traj_out, c->traj, 4 * n * (T + 1) * s.dx, hipMemcpyDeviceToDevice, st));
     if (stats) HIP_TRY(hipMemcpyAsync(stats, c->stats, sizeof(d4_stats), hipMemcpyDeviceToHost, st));
+    return D4_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ tuning
+namespace d4host {
+
+namespace {
+std::mutex g_tile_mu;
+std::map<std::tuple<int, int, int>, Tile> g_tiles;
+}  // namespace
+
+bool tile_override(int dyn, int n, int T, Tile* out) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tiles.find(std::make_tuple(dyn, n, T));
+    if (it == g_tiles.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+}  // namespace d4host
+
+namespace {
+
+int tile_ok(const d4_problem* p, Tile t) {
+    const int cs = shape_of(p->dyn).du == 2 ? 2 : 4;
+    if (t.S < 1 || t.S > 64 || t.S * p->n_robots > 1024) return fail(D4_EINVAL, "samples per group %d invalid", t.S);
+    if (t.Tb < cs || t.Tb > 64 || t.Tb % cs) return fail(D4_EINVAL, "steps per block %d invalid", t.Tb);
+    if (rollfit_lds(p, t) > 160 * 1024) return fail(D4_EUNSUPPORTED, "tile needs too much LDS");
+    return D4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samples_per_group,
+                    int32_t steps_per_block) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    const auto key = std::make_tuple((int)dyn, (int)n_robots, (int)horizon);
+    if (samples_per_group == 0) {
+        g_tiles.erase(key);
+        return D4_OK;
+    }
+    d4_problem p;
+    std::memset(&p, 0, sizeof p);
+    p.dyn = dyn;
+    p.n_robots = n_robots;
+    p.horizon = horizon;
+    if (dyn < 0 || dyn > 2 || n_robots < 1 || n_robots > 32 || horizon < 1)
+        return fail(D4_EINVAL, "bad problem shape");
+    const Tile t{samples_per_group, steps_per_block};
+    int rc = tile_ok(&p, t);
+    if (rc) return rc;
+    g_tiles[key] = t;
+    return D4_OK;
+}
+
+int32_t d4_autotune(const d4_problem* p, int32_t reps, int32_t* samples_per_group, int32_t* steps_per_block,
+                    float* best_us) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (reps < 1) reps = 5;
+    const Shape s = shape_of(p->dyn);
+    const size_t n = p->n_robots, T = p->horizon, M = p->n_samples, D = n * T * s.du;
+    float *eps = nullptr, *r = nullptr, *x0 = nullptr, *goal = nullptr, *ub = nullptr;
+    int* hits = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        for (void* q : {(void*)eps, (void*)r, (void*)x0, (void*)goal, (void*)ub, (void*)hits})
+            if (q) (void)hipFree(q);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&eps, 4 * D * M) != hipSuccess || hipMalloc(&r, 4 * M) != hipSuccess ||
+        hipMalloc(&hits, 4 * M) != hipSuccess || hipMalloc(&x0, 4 * n * s.dx) != hipSuccess ||
+        hipMalloc(&goal, 4 * n * s.dp) != hipSuccess || hipMalloc(&ub, 4 * D) != hipSuccess) {
+        release();
+        return fail(D4_ENOMEM, "autotune scratch allocation failed");
+    }
+    (void)hipMemset(x0, 0, 4 * n * s.dx);
+    (void)hipMemset(goal, 0, 4 * n * s.dp);
+    (void)hipMemset(ub, 0, 4 * D);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const Schedule sc = make_schedule(p);
+    float best = 1e30f;
+    Tile best_t = default_tile(p->dyn, p->n_robots);
+    const int cs = s.du == 2 ? 2 : 4;
+    for (int S : {4, 8, 16, 32, 64}) {
+        for (int Tb : {2, 4, 8, 12, 16}) {
+            const Tile t{S, Tb};
+            if (tile_ok(p, t)) continue;
+            if (Tb % cs) continue;
+            RollFitArgs a = base_args(p, t);
+            a.x0 = x0;
+            a.goal = goal;
+            a.u_base = ub;
+            a.du_in = ub;
+            a.eps = eps;
+            a.r = r;
+            a.hits = hits;
+            a.step = (uint32_t)p->n_steps;
+            a.mean_scale = sc.ms[p->n_steps];
+            a.sigma = sc.sigma[p->n_steps];
+            rc = launch_rollfit<false>(p, a, t, 0);
+            if (rc) continue;
+            (void)hipEventRecord(e0, 0);
+            for (int k = 0; k < reps; ++k) launch_rollfit<false>(p, a, t, 0);
+            (void)hipEventRecord(e1, 0);
+            if (hipEventSynchronize(e1) != hipSuccess) continue;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const float us = ms * 1000.0f / reps;
+            if (us < best) {
+                best = us;
+                best_t = t;
+            }
+        }
+    }
+    release();
+    if (best >= 1e30f) return fail(D4_EHIP, "no tile could be timed");
+    rc = d4_tile_set(p->dyn, p->n_robots, p->horizon, best_t.S, best_t.Tb);
+    if (rc) return rc;
+    if (samples_per_group) *samples_per_group = best_t.S;
+    if (steps_per_block) *steps_per_block = best_t.Tb;
+    if (best_us) *best_us = best;
     return D4_OK;
 }
 

@@ -162,9 +162,14 @@ inline Tile default_tile(int dyn, int n) {
     return {S, Tb};
 }
 
+// Tuned tile of a problem shape installed by d4_tile_set / d4_autotune, if any.
+bool tile_override(int dyn, int n, int T, Tile* out);
+
 inline Tile pick_tile(const d4_problem* p) {
     const int n = p->n_robots;
     Tile t = default_tile(p->dyn, n);
+    Tile o;
+    if (tile_override(p->dyn, n, p->horizon, &o)) t = o;
     int S = t.S, Tb = t.Tb;
     const char* env = std::getenv("D4_TILE_S");
     if (env) {
@@ -173,8 +178,10 @@ inline Tile pick_tile(const d4_problem* p) {
     }
     const char* envt = std::getenv("D4_TILE_TB");
     if (envt) {
+        // the fused kernel walks a time block in whole draw chunks
+        const int cs = shape_of(p->dyn).du == 2 ? 2 : 4;
         int v = std::atoi(envt);
-        if (v >= 1 && v <= 64) Tb = v;
+        if (v >= cs && v <= 64 && v % cs == 0) Tb = v;
     }
     return {S, Tb};
 }

@@ -320,3 +320,25 @@ def test_phase_free_and_general_draw_windows_agree(L):
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-6)
     assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_autotuned_tile_keeps_parity(L, tmp_path):
+    """A tuned tile changes speed, not the method: draws stay bit-exact and the
+    chain still meets the bar; the cache round-trips."""
+    from paper_2503_12204_amd import autotune as AT
+    p, x0, g = W.unicycle_random(n=8, horizon=40, n_samples=512)
+    path = str(tmp_path / "tiles.json")
+    e = AT.tune(p, path=path, reps=2)
+    assert 1 <= e["S"] <= 64 and e["Tb"] % 2 == 0 and e["us"] > 0
+    try:
+        assert AT.tune(p, path=path) == e          # served from the cache
+        assert AT.install_cache(path) == 1
+        rng = np.random.default_rng(3)
+        ub = _rand_controls(rng, p, 1, spread=0.5)[0].reshape(-1)
+        du = (rng.normal(size=p.D) * 0.3).astype(np.float32)
+        eps, r, hits = L.sample_rollout_fitness(p, _cu(x0), _cu(g), _cu(ub), _cu(du), 0, 50)
+        ora = ombd.sample_rewards(p, x0, g, ub, du, 0, 50)
+        assert np.array_equal(_np(eps), ora["eps"])
+        _check_rewards(p, ora, _np(r), _np(hits))
+    finally:
+        AT.clear_tile(p.dyn, p.n_robots, p.horizon)
