@@ -170,23 +170,32 @@ int32_t d4_denoise_iter(d4_ctx* ctx, const d4_problem* p, const float* x0, const
 /* ------------------------------------------------------------------------
  * Launch-shape tuning of the reward kernels (d4_sample_rollout_fitness,
  * d4_fitness, d4_denoise_iter).  A tile is the number of samples per
- * workgroup (1..64, times n_robots at most 1024 lanes) and the number of
- * steps per LDS time block (a multiple of 2 for d_u = 2, of 4 for d_u = 3).
- * The choice changes only speed and the grouping of the reward statistics
- * (so results change in the last bits); the batched form keeps its own rule.
+ * workgroup S (1..64), the number of steps per LDS time block (a multiple of
+ * 2 for d_u = 2, of 4 for d_u = 3) and the replica lanes R per (sample,
+ * robot) (1..8; R > 1 lets R lanes share the draws and pair checks of one
+ * lane, for problems with too few lanes to fill the GPU), with
+ * R * S * n_robots <= 1024.  S changes the grouping of the reward statistics
+ * (results change in the last bits); the time block and R change only speed.
+ * The batched form keeps its own rule (R = 1).
  * ------------------------------------------------------------------------ */
 
 /* Install (or, with samples_per_group = 0, remove) a process-wide tile for
  * problems of this (dyn, n_robots, horizon). */
 int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samples_per_group,
-                    int32_t steps_per_block);
+                    int32_t steps_per_block, int32_t replicas);
+
+/* The tile the library uses for p: the batched form's rule when batched is
+ * non-zero, else the single-problem choice (installed tile or default).
+ * Outputs are host pointers, each may be NULL. */
+int32_t d4_tile_get(const d4_problem* p, int32_t batched, int32_t* samples_per_group, int32_t* steps_per_block,
+                    int32_t* replicas);
 
 /* Time every admissible tile on the current device with the fused kernel of
  * problem p (scratch buffers are allocated and freed here; synchronises the
  * null stream), install the fastest and report it (outputs are host
  * pointers, each may be NULL). */
 int32_t d4_autotune(const d4_problem* p, int32_t reps, int32_t* samples_per_group, int32_t* steps_per_block,
-                    float* best_us);
+                    int32_t* replicas, float* best_us);
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent problems advanced together.  Each instance

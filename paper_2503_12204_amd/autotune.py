@@ -20,10 +20,13 @@ from . import _lib as L
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "d4orm_mi355x_tiles.json")
 
-L.lib().d4_tile_set.argtypes = [ctypes.c_int32] * 5
+_I = ctypes.POINTER(ctypes.c_int32)
+L.lib().d4_tile_set.argtypes = [ctypes.c_int32] * 6
 L.lib().d4_tile_set.restype = ctypes.c_int32
-L.lib().d4_autotune.argtypes = [ctypes.POINTER(L.D4Problem), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
+L.lib().d4_tile_get.argtypes = [ctypes.POINTER(L.D4Problem), ctypes.c_int32, _I, _I, _I]
+L.lib().d4_tile_get.restype = ctypes.c_int32
+L.lib().d4_autotune.argtypes = [ctypes.POINTER(L.D4Problem), ctypes.c_int32, _I, _I, _I,
+                                ctypes.POINTER(ctypes.c_float)]
 L.lib().d4_autotune.restype = ctypes.c_int32
 
 
@@ -50,12 +53,20 @@ def _load(path):
     return {}
 
 
-def set_tile(dyn, n, horizon, samples_per_group, steps_per_block):
-    L._check(L.lib().d4_tile_set(dyn, n, horizon, samples_per_group, steps_per_block))
+def set_tile(dyn, n, horizon, samples_per_group, steps_per_block, replicas=1):
+    L._check(L.lib().d4_tile_set(dyn, n, horizon, samples_per_group, steps_per_block, replicas))
 
 
 def clear_tile(dyn, n, horizon):
-    L._check(L.lib().d4_tile_set(dyn, n, horizon, 0, 0))
+    L._check(L.lib().d4_tile_set(dyn, n, horizon, 0, 0, 0))
+
+
+def get_tile(p, batched=False):
+    """(samples per group, steps per block, replicas) the library uses for p."""
+    S, Tb, R = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    c = L.to_c(p)
+    L._check(L.lib().d4_tile_get(ctypes.byref(c), int(batched), ctypes.byref(S), ctypes.byref(Tb), ctypes.byref(R)))
+    return S.value, Tb.value, R.value
 
 
 def tune(p, path=DEFAULT_CACHE, reps=5, force=False):
@@ -64,12 +75,13 @@ def tune(p, path=DEFAULT_CACHE, reps=5, force=False):
     key = _key(p)
     if key in cache and not force:
         e = cache[key]
-        set_tile(p.dyn, p.n_robots, p.horizon, e["S"], e["Tb"])
+        set_tile(p.dyn, p.n_robots, p.horizon, e["S"], e["Tb"], e.get("R", 1))
         return e
-    S, Tb, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    S, Tb, R, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
     c = L.to_c(p)
-    L._check(L.lib().d4_autotune(ctypes.byref(c), reps, ctypes.byref(S), ctypes.byref(Tb), ctypes.byref(us)))
-    e = {"S": S.value, "Tb": Tb.value, "us": us.value, "n_samples": p.n_samples}
+    L._check(L.lib().d4_autotune(ctypes.byref(c), reps, ctypes.byref(S), ctypes.byref(Tb), ctypes.byref(R),
+                                 ctypes.byref(us)))
+    e = {"S": S.value, "Tb": Tb.value, "R": R.value, "us": us.value, "n_samples": p.n_samples}
     cache[key] = e
     os.makedirs(os.path.dirname(path), exist_ok=True)
     tmp = path + ".tmp"
@@ -86,6 +98,6 @@ def install_cache(path=DEFAULT_CACHE):
     for key, e in _load(path).items():
         if key.startswith(prefix):
             dyn, n, T = (int(v) for v in key[len(prefix):].split("|"))
-            set_tile(dyn, n, T, e["S"], e["Tb"])
+            set_tile(dyn, n, T, e["S"], e["Tb"], e.get("R", 1))
             k += 1
     return k

@@ -42,9 +42,28 @@ void launch_rollfit_dyn(bool from_x, bool aligned, dim3 grid, dim3 block, size_t
 template <bool FROM_X>
 int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStream_t st) {
     const dim3 grid((p->n_samples + tile.S - 1) / tile.S);
-    const dim3 block(tile.S * p->n_robots);
+    if (FROM_X) tile.R = 1;
+    const dim3 block(tile.R * tile.S * p->n_robots);
     const size_t lds = rollfit_lds(p, tile);
     if (lds > 160 * 1024) return fail(D4_EUNSUPPORTED, "reward kernel needs %zu bytes of LDS", lds);
+    if (tile.R > 1) {
+        switch (p->dyn) {
+            case HOLO2D:
+                allow_lds(k_rollfit_coop<HOLO2D>, lds);
+                hipLaunchKernelGGL(k_rollfit_coop<HOLO2D>, grid, block, lds, st, a, tile.R);
+                break;
+            case HOLO3D:
+                allow_lds(k_rollfit_coop<HOLO3D>, lds);
+                hipLaunchKernelGGL(k_rollfit_coop<HOLO3D>, grid, block, lds, st, a, tile.R);
+                break;
+            default:
+                allow_lds(k_rollfit_coop<UNICYCLE>, lds);
+                hipLaunchKernelGGL(k_rollfit_coop<UNICYCLE>, grid, block, lds, st, a, tile.R);
+                break;
+        }
+        HIP_LAUNCH_CHECK("k_rollfit_coop");
+        return D4_OK;
+    }
     const bool al = draws_aligned(p) && !std::getenv("D4_NO_ALIGNED");
     switch (p->dyn) {
         case HOLO2D: launch_rollfit_dyn<HOLO2D>(FROM_X, al, grid, block, lds, st, a); break;
@@ -322,7 +341,7 @@ int32_t d4_score_update(const d4_problem* p, const float* r, const float* eps, c
     const int P = (p->n_samples + S - 1) / S;
     float4* partials = nullptr;
     HIP_TRY(hipMallocAsync((void**)&partials, sizeof(float4) * (size_t)P, st));
-    hipLaunchKernelGGL(k_reward_partials, dim3(P), dim3(64), 0, st, r, p->n_samples, S, partials);
+    hipLaunchKernelGGL(k_reward_partials, dim3((P + 63) / 64), dim3(64), 0, st, r, p->n_samples, S, partials);
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) {
         (void)hipFreeAsync(partials, st);
@@ -473,6 +492,7 @@ namespace {
 int tile_ok(const d4_problem* p, Tile t) {
     const int cs = shape_of(p->dyn).du == 2 ? 2 : 4;
     if (t.S < 1 || t.S > 64 || t.S * p->n_robots > 1024) return fail(D4_EINVAL, "samples per group %d invalid", t.S);
+    if (t.R < 1 || t.R > 8 || t.R * t.S * p->n_robots > 1024) return fail(D4_EINVAL, "replicas %d invalid", t.R);
     if (t.Tb < cs || t.Tb > 64 || t.Tb % cs) return fail(D4_EINVAL, "steps per block %d invalid", t.Tb);
     if (rollfit_lds(p, t) > 160 * 1024) return fail(D4_EUNSUPPORTED, "tile needs too much LDS");
     return D4_OK;
@@ -483,7 +503,7 @@ int tile_ok(const d4_problem* p, Tile t) {
 extern "C" {
 
 int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samples_per_group,
-                    int32_t steps_per_block) {
+                    int32_t steps_per_block, int32_t replicas) {
     std::lock_guard<std::mutex> lk(g_tile_mu);
     const auto key = std::make_tuple((int)dyn, (int)n_robots, (int)horizon);
     if (samples_per_group == 0) {
@@ -497,15 +517,29 @@ int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samp
     p.horizon = horizon;
     if (dyn < 0 || dyn > 2 || n_robots < 1 || n_robots > 32 || horizon < 1)
         return fail(D4_EINVAL, "bad problem shape");
-    const Tile t{samples_per_group, steps_per_block};
+    Tile t;
+    t.S = samples_per_group;
+    t.Tb = steps_per_block;
+    t.R = replicas;
     int rc = tile_ok(&p, t);
     if (rc) return rc;
     g_tiles[key] = t;
     return D4_OK;
 }
 
+int32_t d4_tile_get(const d4_problem* p, int32_t batched, int32_t* samples_per_group, int32_t* steps_per_block,
+                    int32_t* replicas) {
+    int rc = validate(p);
+    if (rc) return rc;
+    const Tile t = batched ? default_tile(p->dyn, p->n_robots) : pick_tile(p);
+    if (samples_per_group) *samples_per_group = t.S;
+    if (steps_per_block) *steps_per_block = t.Tb;
+    if (replicas) *replicas = t.R;
+    return D4_OK;
+}
+
 int32_t d4_autotune(const d4_problem* p, int32_t reps, int32_t* samples_per_group, int32_t* steps_per_block,
-                    float* best_us) {
+                    int32_t* replicas, float* best_us) {
     int rc = validate(p);
     if (rc) return rc;
     if (reps < 1) reps = 5;
@@ -535,11 +569,15 @@ int32_t d4_autotune(const d4_problem* p, int32_t reps, int32_t* samples_per_grou
     float best = 1e30f;
     Tile best_t = default_tile(p->dyn, p->n_robots);
     const int cs = s.du == 2 ? 2 : 4;
-    for (int S : {4, 8, 16, 32, 64}) {
-        for (int Tb : {2, 4, 8, 12, 16}) {
-            const Tile t{S, Tb};
-            if (tile_ok(p, t)) continue;
+    for (int R : {1, 2, 4}) for (int S : {4, 8, 16, 32, 64}) {
+        for (int Tb : {2, 4, 8, 12, 16, 32}) {
+            Tile t;
+            t.S = S;
+            t.Tb = Tb;
+            t.R = R;
             if (Tb % cs) continue;
+            if (R > 1 && S * p->n_robots * R < 64) continue;
+            if (tile_ok(p, t)) continue;
             RollFitArgs a = base_args(p, t);
             a.x0 = x0;
             a.goal = goal;
@@ -568,10 +606,11 @@ int32_t d4_autotune(const d4_problem* p, int32_t reps, int32_t* samples_per_grou
     }
     release();
     if (best >= 1e30f) return fail(D4_EHIP, "no tile could be timed");
-    rc = d4_tile_set(p->dyn, p->n_robots, p->horizon, best_t.S, best_t.Tb);
+    rc = d4_tile_set(p->dyn, p->n_robots, p->horizon, best_t.S, best_t.Tb, best_t.R);
     if (rc) return rc;
     if (samples_per_group) *samples_per_group = best_t.S;
     if (steps_per_block) *steps_per_block = best_t.Tb;
+    if (replicas) *replicas = best_t.R;
     if (best_us) *best_us = best;
     return D4_OK;
 }

@@ -145,18 +145,19 @@ inline StepConsts step_consts(const d4_problem* p) {
 
 struct Tile {
     int S, Tb;
+    int R = 1;  // replica lanes per (sample, robot); R > 1 selects the cooperative kernel
 };
 
 // Samples per workgroup and time-block length of the reward kernels.  One
 // rule serves the single-problem and the batched kernels (workgroups of at most
 // 256 lanes), so a batched instance reproduces its single-problem run bit for
 // bit: S = min(64, floor(256 / n)) samples, and a time block that keeps the
-// double-buffered positions near 32 KiB, in whole draw chunks.
+// double-buffered positions near 64 KiB, in whole draw chunks.
 inline Tile default_tile(int dyn, int n) {
     int S = std::min(64, 256 / n);
     const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
-    const int per_step = 2 * n * S * slot;
-    int Tb = (32 * 1024) / per_step;
+    const int per_step = 2 * (2 * n - 1) * S * slot;
+    int Tb = (64 * 1024) / per_step;
     const int cs = shape_of(dyn).du == 2 ? 2 : 4;
     Tb = std::max(cs, std::min(16, Tb / cs * cs));
     return {S, Tb};
@@ -165,9 +166,27 @@ inline Tile default_tile(int dyn, int n) {
 // Tuned tile of a problem shape installed by d4_tile_set / d4_autotune, if any.
 bool tile_override(int dyn, int n, int T, Tile* out);
 
+// Single-problem default: halve the samples per workgroup until there are at
+// least 256 workgroups (one per CU), then add replica lanes (cooperative
+// kernel) up to 256 lanes per workgroup when a workgroup would be smaller.
+inline Tile single_tile(int dyn, int n, int M) {
+    Tile t = default_tile(dyn, n);
+    int S = t.S;
+    while (S > 1 && (M + S - 1) / S < 256) S >>= 1;
+    if (S == t.S) return t;
+    const int R = std::max(1, std::min(4, 256 / (S * n)));
+    const int cs = shape_of(dyn).du == 2 ? 2 : 4;
+    const int Tb = R > 1 ? 16 : std::max(cs, std::min(16, ((64 * 1024) / (2 * (2 * n - 1) * S * 16)) / cs * cs));
+    Tile out;
+    out.S = S;
+    out.Tb = Tb;
+    out.R = R;
+    return out;
+}
+
 inline Tile pick_tile(const d4_problem* p) {
     const int n = p->n_robots;
-    Tile t = default_tile(p->dyn, n);
+    Tile t = single_tile(p->dyn, n, p->n_samples);
     Tile o;
     if (tile_override(p->dyn, n, p->horizon, &o)) t = o;
     int S = t.S, Tb = t.Tb;
@@ -183,14 +202,32 @@ inline Tile pick_tile(const d4_problem* p) {
         int v = std::atoi(envt);
         if (v >= cs && v <= 64 && v % cs == 0) Tb = v;
     }
-    return {S, Tb};
+    int R = t.R;
+    const char* envr = std::getenv("D4_TILE_R");
+    if (envr) {
+        int v = std::atoi(envr);
+        if (v >= 1 && v <= 8) R = v;
+    }
+    if (R * S * n > 1024) R = std::max(1, 1024 / (S * n));
+    Tile out;
+    out.S = S;
+    out.Tb = Tb;
+    out.R = R;
+    return out;
 }
 
 inline size_t rollfit_lds(const d4_problem* p, Tile t) {
     const Shape s = shape_of(p->dyn);
     const size_t n = p->n_robots;
     const size_t slot = s.dp == 3 ? 16 : 8;
-    const size_t a = (size_t)2 * t.Tb * n * t.S * slot + (size_t)2 * t.Tb * t.S * 4;
+    const size_t n2 = 2 * n - 1;  // position slots per step
+    if (t.R > 1) {  // cooperative kernel: draws, single-buffered positions, masks
+        const size_t G = (size_t)t.Tb * s.du / 4 + 1;
+        const size_t a = n * G * 4 * t.S * 4 + (size_t)t.Tb * n2 * t.S * slot + (size_t)2 * t.Tb * t.S * 4;
+        const size_t b = (size_t)(2 + t.R) * n * t.S * 4;
+        return a > b ? a : b;
+    }
+    const size_t a = (size_t)2 * t.Tb * n2 * t.S * slot + (size_t)2 * t.Tb * t.S * 4;
     const size_t b = (size_t)3 * n * t.S * 4;
     return a > b ? a : b;
 }

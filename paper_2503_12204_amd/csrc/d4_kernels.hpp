@@ -14,7 +14,8 @@
 // Lane mapping of k_rollfit: one lane per (sample m, robot k) with the sample
 // index fastest, S samples per workgroup (blockDim = n*S).  A lane keeps its
 // robot's state in registers and walks t = 0..T-1; positions of a block of Tb
-// steps go to LDS as [Tb][n][S] float2/float4 slots so that the pair checks of
+// steps go to LDS as [Tb][2n-1][S] float2/float4 slots (robots 0..n-1, then
+// 0..n-2 again, so a lane's partners are contiguous) and the pair checks of
 // one step read consecutive slots across a wave.  Lane k checks partners (k + j) mod n
 // for j = 1..floor((n-1)/2), plus j = n/2 for k < n/2 when n is even: every
 // unordered pair exactly once, spread evenly.  The per-(m, t) "robot k hit
@@ -36,6 +37,25 @@ __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     return v;
+}
+
+// Statistics (count, mean, M2, max) of n <= 64 rewards, one thread, fixed
+// order.  Used by every producer of reward statistics so that they agree bit
+// for bit; a single thread avoids cross-lane reads in partially filled waves.
+__device__ __forceinline__ float4 reward_stats_seq(const float* r, int n) {
+    float s = 0.0f, mx = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        s += r[i];
+        mx = fmaxf(mx, r[i]);
+    }
+    const float cnt = (float)n;
+    const float mean = n > 0 ? s / cnt : 0.0f;
+    float m2 = 0.0f;
+    for (int i = 0; i < n; ++i) {
+        const float d = r[i] - mean;
+        m2 += d * d;
+    }
+    return make_float4(cnt, mean, m2, mx);
 }
 
 struct RollFitArgs {
@@ -86,6 +106,43 @@ struct PosSlot<3> {
 // (T * d_u % 4 == 0), so the draw window needs no phase selection.
 enum { MODE_FUSED = 1, MODE_FROM_X = 2, MODE_FUSED_ALIGNED = 3 };
 
+// Collision bits of robot k at one step: bit l set when partner l = k + j
+// (mod n), j = 1..jmax, is within the reward threshold.  pb points at slot 0
+// of this sample's step; the step holds 2n - 1 slots (robots 0..n-1, then
+// 0..n-2 again, S apart), so the partners are contiguous.  Hits are collected
+// at unwrapped positions k + j < 2n and folded back modulo n.
+template <int DP>
+__device__ __forceinline__ uint32_t pair_bits(const typename PosSlot<DP>::T* pb, int n, int S, int k, int jmax,
+                                              float thr2) {
+    using PS = PosSlot<DP>;
+    float pk[DP];
+    PS::unpack(pb[k * S], pk);
+    const typename PS::T* q = pb + (k + 1) * S;
+    const uint32_t low = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
+    if (n <= 16) {
+        uint32_t bits = 0u, bit = 2u << k;
+#pragma unroll 4
+        for (int j = 0; j < jmax; ++j) {
+            float pl[DP];
+            PS::unpack(*q, pl);
+            bits |= (pair_d2<DP>(pk, pl) <= thr2) ? bit : 0u;
+            q += S;
+            bit <<= 1;
+        }
+        return (bits | (bits >> n)) & low;
+    }
+    uint64_t bits = 0ull, bit = 2ull << k;
+#pragma unroll 4
+    for (int j = 0; j < jmax; ++j) {
+        float pl[DP];
+        PS::unpack(*q, pl);
+        bits |= (pair_d2<DP>(pk, pl) <= thr2) ? bit : 0ull;
+        q += S;
+        bit <<= 1;
+    }
+    return (uint32_t)((bits | (bits >> n)) & low);
+}
+
 // Steps per noise chunk (a whole number of Philox blocks) and blocks per chunk.
 template <int DU>
 struct Chunk {
@@ -115,8 +172,9 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
     const int m = m0 + ms;
     const bool live = active && m < M;
     const int mc = m < M ? m : M - 1;
-    PT* pos = reinterpret_cast<PT*>(lds);                                        // [2][Tb][n][S]
-    uint32_t* mask = reinterpret_cast<uint32_t*>(pos + 2 * Tb * n * S);          // [2][Tb][S]
+    const int n2 = 2 * n - 1;                                                    // slots per step
+    PT* pos = reinterpret_cast<PT*>(lds);                                        // [2][Tb][2n-1][S]
+    uint32_t* mask = reinterpret_cast<uint32_t*>(pos + 2 * Tb * n2 * S);         // [2][Tb][S]
 
     float x[DX], aux[DY::AUX], g[DP];
     if (FROM_X) {
@@ -162,7 +220,12 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
 #pragma unroll
         for (int c = 0; c < DP; ++c) dist2 += (x[c] - g[c]) * (x[c] - g[c]);
         goal_acc += 1.0f - fast_sqrt(dist2) * inv_d0;
-        if (active) pos[((buf * Tb + tt) * n + k) * S + ms] = PS::pack(x);
+        if (active) {
+            const PT v = PS::pack(x);
+            PT* slot = pos + ((buf * Tb + tt) * n2 + k) * S + ms;
+            slot[0] = v;
+            if (k < n - 1) slot[n * S] = v;
+        }
     };
 
     const int nblk = (T + Tb - 1) / Tb;
@@ -226,25 +289,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
             for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
         __syncthreads();
         for (int tt = 0; tt < tcount; ++tt) {
-            const PT* pb = pos + (buf * Tb + tt) * n * S + ms;
-            const PT* pend = pb + n * S;
-            const PT* q = pb + k * S;
-            float pk[DP];
-            PS::unpack(*q, pk);
-            uint32_t bits = 0u;
-            int l = k;
-#pragma unroll 4
-            for (int j = 0; j < jmax; ++j) {
-                q += S;
-                ++l;
-                if (q == pend) {
-                    q = pb;
-                    l = 0;
-                }
-                float pl[DP];
-                PS::unpack(*q, pl);
-                bits |= (pair_d2<DP>(pk, pl) <= a.thr2) ? (1u << l) : 0u;
-            }
+            const uint32_t bits = pair_bits<DP>(pos + (buf * Tb + tt) * n2 * S + ms, n, S, k, jmax, a.thr2);
             hit_cnt += __popc(bits);
             if (bits) atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));
         }
@@ -278,23 +323,174 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
         if (a.robots_hit) a.robots_hit[m] = ss;
         rg[ms] = rv;
     }
-    if (a.partials && tid < 64) {
-        // statistics of this tile's rewards (S <= 64 lanes of wave 0)
-        const bool mine = tid < S && (m0 + tid) < M;
-        const float rv = mine ? rg[tid] : 0.0f;
-        const float cnt = wave_sum(mine ? 1.0f : 0.0f);
-        const float mean = wave_sum(rv) / cnt;
-        const float dv = mine ? rv - mean : 0.0f;
-        const float m2 = wave_sum(dv * dv);
-        const float mx = wave_max(mine ? rv : -INFINITY);
-        if (tid == 0) a.partials[part] = make_float4(cnt, mean, m2, mx);
-    }
+    __syncthreads();
+    if (a.partials && tid == 0) a.partials[part] = reward_stats_seq(rg, min(S, M - m0));
 }
 
 template <int DYN, int MODE>
 __global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
     extern __shared__ float lds[];
     rollfit_tile<DYN, MODE>(a, blockIdx.x * a.S, blockIdx.x, lds);
+}
+
+// Cooperative variant of the fused kernel for problems with few (sample,
+// robot) lanes: R replica lanes per (sample, robot).  Per time block of Tb
+// steps: (1) all replicas generate the robot's draws of the block, whole
+// Philox blocks, into LDS (and eps); (2) replica 0 rolls the robot out over
+// the block, reading its draws from LDS; (3) all replicas share the pair
+// checks, step tt going to replica tt mod R; (4) replica 0 reads the collision
+// masks.  Every value is computed as in the one-lane kernel and every sum is
+// taken in the same order, so the results are identical to it.
+// Lanes: tid = rep * (n*S) + k * S + ms.  LDS: draws [n][G][4][S] floats with
+// G = Tb*d_u/4 + 1, positions [Tb][2n-1][S] slots, masks [2][Tb][S].
+template <int DYN, int MODE>
+__device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, int m0, int part, float* lds) {
+    using DY = Dyn<DYN>;
+    constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
+    using PS = PosSlot<DP>;
+    using PT = typename PS::T;
+    const int n = a.n, T = a.T, M = a.M, S = a.S, Tb = a.Tb;
+    const int G = Tb * DU / 4 + 1;
+    const int tid = threadIdx.x;
+    const int group = n * S;
+    const int rep = tid / group;
+    const int local = tid - rep * group;
+    const bool active = rep < R;
+    const int k = local / S;
+    const int ms = local - k * S;
+    const int m = m0 + ms;
+    const bool live = active && m < M;
+    const int mc = m < M ? m : M - 1;
+    const int n2 = 2 * n - 1;
+    float* nz = lds;                                                           // [n][G][4][S]
+    PT* pos = reinterpret_cast<PT*>(nz + (size_t)n * G * 4 * S);              // [Tb][2n-1][S]
+    uint32_t* mask = reinterpret_cast<uint32_t*>(pos + (size_t)Tb * n2 * S); // [2][Tb][S]
+
+    float x[DX], aux[DY::AUX], g[DP];
+#pragma unroll
+    for (int c = 0; c < DX; ++c) x[c] = a.x0[k * DX + c];
+    DY::init(x, aux);
+#pragma unroll
+    for (int c = 0; c < DP; ++c) g[c] = a.goal[k * DP + c];
+    float d0s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < DP; ++c) d0s += (x[c] - g[c]) * (x[c] - g[c]);
+    const float inv_d0 = 1.0f / fmaxf(fast_sqrt(d0s), a.d0_floor);
+    float goal_acc = 0.0f;
+    int safe_cnt = 0, hit_cnt = 0;
+    const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
+    const uint32_t c2 = (iter << 16) | a.step;
+    const uint32_t ebase = (uint32_t)(k * T * DU);
+    float ulo[DU], uhi[DU];
+#pragma unroll
+    for (int d = 0; d < DU; ++d) {
+        ulo[d] = a.ulo[d];
+        uhi[d] = a.uhi[d];
+    }
+    const float sigma = a.sigma, mscale = a.mean_scale;
+    const int jmax = active ? ((n - 1) >> 1) + ((((n & 1) == 0) && (k < (n >> 1))) ? 1 : 0) : 0;
+    const bool pairs_mode = (a.flags & FLAG_SAFE_PAIRS) != 0;
+    const size_t Ms = (size_t)M;
+    float* nzk = nz + (size_t)k * G * 4 * S + ms;
+
+    const int nblk = (T + Tb - 1) / Tb;
+    for (int b = 0; b < nblk; ++b) {
+        const int buf = b & 1;
+        const int t0 = b * Tb;
+        const int tcount = min(Tb, T - t0);
+        const uint32_t e_lo = ebase + (uint32_t)(t0 * DU);
+        const uint32_t e_hi = e_lo + (uint32_t)(tcount * DU);
+        const uint32_t g_a = e_lo >> 2;
+        const int G_b = (int)(((e_hi - 1) >> 2) - g_a) + 1;
+        // (1) draws of this block
+        if (active) {
+            for (int gi = rep; gi < G_b; gi += R) {
+                float z[4];
+                normal_block(g_a + (uint32_t)gi, (uint32_t)mc, c2, a.inst, a.key0, a.key1, z[0], z[1], z[2], z[3]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    nzk[(size_t)(gi * 4 + j) * S] = z[j];
+                    const uint32_t e = 4 * (g_a + (uint32_t)gi) + (uint32_t)j;
+                    if (live && e >= e_lo && e < e_hi) a.eps[(size_t)e * Ms + m] = z[j];
+                }
+            }
+        }
+        if (rep == 0 && k == 0 && active)
+            for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
+        __syncthreads();
+        // (2) rollout of the block by replica 0
+        if (rep == 0 && active) {
+            for (int tt = 0; tt < tcount; ++tt) {
+                const int t = t0 + tt;
+                float u[DU];
+#pragma unroll
+                for (int d = 0; d < DU; ++d) {
+                    const uint32_t e = ebase + (uint32_t)(t * DU + d);
+                    const float z = nzk[(size_t)(((e >> 2) - g_a) * 4 + (e & 3u)) * S];
+                    const float cb = a.u_base[e] + a.du_in[e] * mscale;
+                    u[d] = fminf(fmaxf(cb + sigma * z, ulo[d]), uhi[d]);
+                }
+                DY::step(x, aux, u, a.sc);
+                float dist2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < DP; ++c) dist2 += (x[c] - g[c]) * (x[c] - g[c]);
+                goal_acc += 1.0f - fast_sqrt(dist2) * inv_d0;
+                const PT v = PS::pack(x);
+                PT* slot = pos + (tt * n2 + k) * S + ms;
+                slot[0] = v;
+                if (k < n - 1) slot[n * S] = v;
+            }
+        }
+        __syncthreads();
+        // (3) pair checks shared by the replicas
+        if (active) {
+            for (int tt = rep; tt < tcount; tt += R) {
+                const uint32_t bits = pair_bits<DP>(pos + tt * n2 * S + ms, n, S, k, jmax, a.thr2);
+                hit_cnt += __popc(bits);
+                if (bits) atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));
+            }
+        }
+        __syncthreads();
+        // (4) collision flags of robot k
+        if (rep == 0 && active)
+            for (int tt = 0; tt < tcount; ++tt) safe_cnt += (mask[(buf * Tb + tt) * S + ms] >> k) & 1u;
+    }
+
+    __syncthreads();
+    float* rg = lds;
+    int* rs = reinterpret_cast<int*>(lds + group);
+    int* rh = rs + group;                  // [R][n][S]
+    if (active) {
+        rh[rep * group + k * S + ms] = hit_cnt;
+        if (rep == 0) {
+            rg[k * S + ms] = goal_acc;
+            rs[k * S + ms] = safe_cnt;
+        }
+    }
+    __syncthreads();
+    if (rep == 0 && k == 0 && live) {
+        float gs = 0.0f;
+        int ss = 0, hs = 0;
+        for (int kk = 0; kk < n; ++kk) {
+            gs += rg[kk * S + ms];
+            ss += rs[kk * S + ms];
+            for (int rr = 0; rr < R; ++rr) hs += rh[rr * group + kk * S + ms];
+        }
+        const float pen = pairs_mode ? (float)(2 * hs) : (float)ss;
+        const float rv = (gs - a.w_safe * pen) / (float)(n * T);
+        a.r[m] = rv;
+        a.hits[m] = hs;
+        if (a.robots_hit) a.robots_hit[m] = ss;
+        rg[ms] = rv;
+    }
+    __syncthreads();
+    if (a.partials && tid == 0) a.partials[part] = reward_stats_seq(rg, min(S, M - m0));
+}
+
+template <int DYN>
+__global__ void __launch_bounds__(1024) k_rollfit_coop(const RollFitArgs a, int R) {
+    extern __shared__ float lds[];
+    rollfit_coop_tile<DYN, MODE_FUSED>(a, R, blockIdx.x * a.S, blockIdx.x, lds);
 }
 
 // eps[e][m] for e < D, m < M; one lane per (Philox block, sample).
@@ -367,16 +563,10 @@ __device__ __forceinline__ float4 wave_combine(float4 v) {
 
 // Reward statistics of consecutive S-sample chunks (S <= 64), computed exactly
 // as the fused kernel's tail computes them for its workgroups of S samples.
-static __global__ void __launch_bounds__(64) k_reward_partials(const float* r, int M, int S, float4* partials) {
-    const int m = blockIdx.x * S + threadIdx.x;
-    const bool mine = (int)threadIdx.x < S && m < M;
-    const float rv = mine ? r[m] : 0.0f;
-    const float cnt = wave_sum(mine ? 1.0f : 0.0f);
-    const float mean = wave_sum(rv) / cnt;
-    const float dv = mine ? rv - mean : 0.0f;
-    const float m2 = wave_sum(dv * dv);
-    const float mx = wave_max(mine ? rv : -INFINITY);
-    if (threadIdx.x == 0) partials[blockIdx.x] = make_float4(cnt, mean, m2, mx);
+static __global__ void k_reward_partials(const float* r, int M, int S, float4* partials) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m0 = b * S;
+    if (m0 < M) partials[b] = reward_stats_seq(r + m0, min(S, M - m0));
 }
 
 struct UpdateArgs {

@@ -37,12 +37,19 @@ def test_batch_equals_single_problem_runs(L):
         stats = bc.iterate(it)
     got = [bc.plan_of(j).cpu().numpy() for j in range(len(probs))]
     bc.close()
+    from paper_2503_12204_amd import autotune as AT
     for j, (p, x0, g) in enumerate(inst):
-        ctx = L.Context(p)
-        u = torch.as_tensor(plans[j], device="cuda").clone()
-        for it in range(2):
-            st = ctx.denoise_iter(torch.as_tensor(x0, device="cuda"), torch.as_tensor(g, device="cuda"), u, it)
-        ctx.close()
+        # the single-problem path with the batched form's tile
+        S, Tb, R = AT.get_tile(p, batched=True)
+        AT.set_tile(p.dyn, p.n_robots, p.horizon, S, Tb, R)
+        try:
+            ctx = L.Context(p)
+            u = torch.as_tensor(plans[j], device="cuda").clone()
+            for it in range(2):
+                st = ctx.denoise_iter(torch.as_tensor(x0, device="cuda"), torch.as_tensor(g, device="cuda"), u, it)
+            ctx.close()
+        finally:
+            AT.clear_tile(p.dyn, p.n_robots, p.horizon)
         assert np.array_equal(u.cpu().numpy(), got[j]), f"instance {j}"
         assert st == stats[j], f"instance {j}"
         fin = ombd.apply_deformation(p, x0, g, got[j], np.zeros(p.D))

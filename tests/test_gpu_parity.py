@@ -342,3 +342,57 @@ def test_autotuned_tile_keeps_parity(L, tmp_path):
         _check_rewards(p, ora, _np(r), _np(hits))
     finally:
         AT.clear_tile(p.dyn, p.n_robots, p.horizon)
+
+
+@pytest.mark.parametrize("dyn,n,T,M,S,Tb", [(W.UNICYCLE, 8, 100, 2048, 8, 16), (W.HOLO3D, 5, 37, 77, 8, 8),
+                                           (W.HOLO2D, 3, 41, 50, 16, 6), (W.HOLO3D, 16, 20, 40, 4, 4)])
+def test_cooperative_kernel_is_bit_identical(L, dyn, n, T, M, S, Tb):
+    """Replica lanes sharing the draws and pair checks reproduce the one-lane
+    kernel exactly: draws, rewards, hit counts and a whole iteration."""
+    from paper_2503_12204_amd import autotune as AT
+    rng = np.random.default_rng(n * T)
+    p, x0, g = W.random_instance(rng, dyn, n, T, M, box=max(3.0, n ** 0.5 * 1.5), min_sep=0.6)
+    p = p.replace(n_steps=6)
+    ub = _cu(_rand_controls(rng, p, 1, spread=0.5)[0].reshape(-1))
+    du = _cu((rng.normal(size=p.D) * 0.3).astype(np.float32))
+    outs, plans = [], []
+    try:
+        for R in (1, 2, 4):
+            if R * S * n > 1024:
+                continue
+            AT.set_tile(p.dyn, n, T, S, Tb, R)
+            outs.append([_np(t) for t in L.sample_rollout_fitness(p, _cu(x0), _cu(g), ub, du, 3, 5)])
+            ctx = L.Context(p)
+            u = torch.zeros((n, T, p.du), dtype=torch.float32, device="cuda")
+            ctx.denoise_iter(_cu(x0), _cu(g), u, 0)
+            ctx.close()
+            plans.append(_np(u))
+    finally:
+        AT.clear_tile(p.dyn, n, T)
+    assert len(outs) >= 2
+    for o, pl in zip(outs[1:], plans[1:]):
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+        assert np.array_equal(plans[0], pl)
+
+
+def test_negative_rewards_in_partial_waves(L):
+    """A packed 3-robot team (collision penalties make rewards negative) with
+    workgroups smaller than a wave: the reward statistics of the fused kernel
+    and of the standalone update agree, so the split calls reproduce the graph
+    iteration bit for bit."""
+    rng = np.random.default_rng(21)
+    p, x0, g = W.random_instance(rng, W.HOLO2D, 3, 30, 70, box=1.6, min_sep=0.5)
+    p = p.replace(n_steps=8, w_safe=3.0)
+    u_base = _rand_controls(rng, p, 1, spread=0.2)[0]
+    eps, r, _ = L.sample_rollout_fitness(p, _cu(x0), _cu(g), _cu(u_base.reshape(-1)),
+                                         torch.zeros(p.D, device="cuda"), 0, 8)
+    assert (_np(r) < 0).all()
+    du0 = _gpu_iteration_stepwise(L, p, x0, g, u_base, 0, set(), [])
+    lo, hi = np.array(p.u_lo[:2], np.float32), np.array(p.u_hi[:2], np.float32)
+    expect = np.minimum(np.maximum(u_base + _np(du0).reshape(u_base.shape), lo), hi)
+    ctx = L.Context(p)
+    u = _cu(u_base)
+    ctx.denoise_iter(_cu(x0), _cu(g), u, 0)
+    ctx.close()
+    assert np.array_equal(_np(u), expect)
