@@ -105,6 +105,15 @@ const char* d4_last_error(void);
 int32_t d4_noise(const d4_problem* p, uint32_t iter, uint32_t step, float* eps, void* stream);
 
 /*
+ * The Box-Muller stage of the d4_noise recipe on given generator words
+ * (sampling step of Algorithm 1): for i < count, words[2i] feeds the radius
+ * and words[2i+1] the angle; z[2i] = rho cos, z[2i+1] = rho sin.  words and
+ * z are device arrays of 2*count elements; count >= 0 (0 launches nothing).
+ * Lets a caller check the transform on every input it can receive.
+ */
+int32_t d4_box_muller(const uint32_t* words, int64_t count, float* z, void* stream);
+
+/*
  * Rollout (Section III feasibility, Section IV-C): x[m][k][0] = x0[k];
  * x[m][k][t+1] = RK4(x[m][k][t], clip(u[m][k][t])) with holonomic speeds
  * clipped per component after each step.
@@ -191,11 +200,13 @@ int32_t d4_tile_get(const d4_problem* p, int32_t batched, int32_t* samples_per_g
                     int32_t* replicas);
 
 /* Time every admissible tile on the current device with the fused kernel of
- * problem p (scratch buffers are allocated and freed here; synchronises the
- * null stream), install the fastest and report it (outputs are host
- * pointers, each may be NULL). */
-int32_t d4_autotune(const d4_problem* p, int32_t reps, int32_t* samples_per_group, int32_t* steps_per_block,
-                    int32_t* replicas, float* best_us);
+ * problem p on the start states x0 [n][d_x] and goals goal [n][d_p] (device
+ * arrays; the broad phase of the pair checks makes the cost depend on where
+ * the robots are), with zero controls.  Scratch buffers are allocated and
+ * freed here; synchronises the null stream.  Installs the fastest tile and
+ * reports it (outputs are host pointers, each may be NULL). */
+int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int32_t reps,
+                    int32_t* samples_per_group, int32_t* steps_per_block, int32_t* replicas, float* best_us);
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent problems advanced together.  Each instance

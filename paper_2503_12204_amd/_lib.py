@@ -51,6 +51,7 @@ def _load():
     sig = {
         "d4_last_error": ([], ctypes.c_char_p),
         "d4_noise": ([P, c_uint32, c_uint32, fp, c_void_p], c_int32),
+        "d4_box_muller": ([fp, ctypes.c_int64, fp, c_void_p], c_int32),
         "d4_rollout": ([P, fp, fp, fp, c_void_p], c_int32),
         "d4_fitness": ([P, fp, fp, fp, fp, fp, c_void_p], c_int32),
         "d4_sample_rollout_fitness": ([P, fp, fp, fp, fp, c_uint32, c_uint32, fp, fp, fp, c_void_p], c_int32),
@@ -120,6 +121,18 @@ def noise(p: Problem, iteration: int, step: int, out=None):
     eps = out if out is not None else torch.empty((p.D, p.n_samples), dtype=torch.float32, device="cuda")
     _check(_lib.d4_noise(ctypes.byref(c), iteration, step, _dev(eps, (p.D, p.n_samples), name="eps"), _stream()))
     return eps
+
+
+def box_muller(words):
+    """Box-Muller stage of the draw recipe on generator words [2*count] (int32
+    or uint32 bits): z[2i] = rho cos, z[2i+1] = rho sin."""
+    if not isinstance(words, torch.Tensor) or not words.is_cuda or words.dim() != 1 or words.numel() % 2:
+        raise TypeError("words must be a 1-D CUDA tensor of even length")
+    if words.dtype not in (torch.int32, torch.uint32) or not words.is_contiguous():
+        raise TypeError("words must be contiguous int32 or uint32")
+    z = torch.empty(words.numel(), dtype=torch.float32, device=words.device)
+    _check(_lib.d4_box_muller(c_void_p(words.data_ptr()), words.numel() // 2, _dev(z, name="z"), _stream()))
+    return z
 
 
 def rollout(p: Problem, x0, u):

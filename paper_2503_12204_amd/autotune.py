@@ -25,8 +25,8 @@ L.lib().d4_tile_set.argtypes = [ctypes.c_int32] * 6
 L.lib().d4_tile_set.restype = ctypes.c_int32
 L.lib().d4_tile_get.argtypes = [ctypes.POINTER(L.D4Problem), ctypes.c_int32, _I, _I, _I]
 L.lib().d4_tile_get.restype = ctypes.c_int32
-L.lib().d4_autotune.argtypes = [ctypes.POINTER(L.D4Problem), ctypes.c_int32, _I, _I, _I,
-                                ctypes.POINTER(ctypes.c_float)]
+L.lib().d4_autotune.argtypes = [ctypes.POINTER(L.D4Problem), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                _I, _I, _I, ctypes.POINTER(ctypes.c_float)]
 L.lib().d4_autotune.restype = ctypes.c_int32
 
 
@@ -69,8 +69,11 @@ def get_tile(p, batched=False):
     return S.value, Tb.value, R.value
 
 
-def tune(p, path=DEFAULT_CACHE, reps=5, force=False):
-    """Tile for problem p: from the cache, else measured now (and cached)."""
+def tune(p, x0, goal, path=DEFAULT_CACHE, reps=5, force=False):
+    """Tile for problem p: from the cache, else measured now on the start
+    states x0 [n][d_x] and goals [n][d_p] (and cached).  The cost of the pair
+    checks depends on how close the robots come, so tune on a representative
+    instance of the shape."""
     cache = _load(path)
     key = _key(p)
     if key in cache and not force:
@@ -79,8 +82,10 @@ def tune(p, path=DEFAULT_CACHE, reps=5, force=False):
         return e
     S, Tb, R, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
     c = L.to_c(p)
-    L._check(L.lib().d4_autotune(ctypes.byref(c), reps, ctypes.byref(S), ctypes.byref(Tb), ctypes.byref(R),
-                                 ctypes.byref(us)))
+    x0_d = L._f32(x0).reshape(p.n_robots, p.dx).contiguous()
+    g_d = L._f32(goal).reshape(p.n_robots, p.dp).contiguous()
+    L._check(L.lib().d4_autotune(ctypes.byref(c), ctypes.c_void_p(x0_d.data_ptr()), ctypes.c_void_p(g_d.data_ptr()),
+                                 reps, ctypes.byref(S), ctypes.byref(Tb), ctypes.byref(R), ctypes.byref(us)))
     e = {"S": S.value, "Tb": Tb.value, "R": R.value, "us": us.value, "n_samples": p.n_samples}
     cache[key] = e
     os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -46,6 +46,8 @@ int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStre
     const dim3 block(tile.R * tile.S * p->n_robots);
     const size_t lds = rollfit_lds(p, tile);
     if (lds > 160 * 1024) return fail(D4_EUNSUPPORTED, "reward kernel needs %zu bytes of LDS", lds);
+    if (tile.S * p->n_robots > 256 || tile.R * tile.S * p->n_robots > 1024)
+        return fail(D4_EINVAL, "workgroup of %d x %d x %d lanes too large", tile.R, tile.S, p->n_robots);
     if (tile.R > 1) {
         switch (p->dyn) {
             case HOLO2D:
@@ -244,6 +246,17 @@ int32_t d4_noise(const d4_problem* p, uint32_t iter, uint32_t step, float* eps, 
                        (iter << 16) | step, p->instance_id, (uint32_t)(p->seed & 0xFFFFFFFFull),
                        (uint32_t)(p->seed >> 32));
     HIP_LAUNCH_CHECK("k_noise");
+    return D4_OK;
+}
+
+int32_t d4_box_muller(const uint32_t* words, int64_t count, float* z, void* stream) {
+    if (count < 0) return fail(D4_EINVAL, "count %lld < 0", (long long)count);
+    if (count == 0) return D4_OK;
+    NEED(words);
+    NEED(z);
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_box_muller, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, words, count, z);
+    HIP_LAUNCH_CHECK("k_box_muller");
     return D4_OK;
 }
 
@@ -491,7 +504,9 @@ namespace {
 
 int tile_ok(const d4_problem* p, Tile t) {
     const int cs = shape_of(p->dyn).du == 2 ? 2 : 4;
-    if (t.S < 1 || t.S > 64 || t.S * p->n_robots > 1024) return fail(D4_EINVAL, "samples per group %d invalid", t.S);
+    // a workgroup holds S samples of all n robots (times R replicas): at most 256 lanes
+    // for the one-lane kernel, 1024 for the cooperative one
+    if (t.S < 1 || t.S > 64 || t.S * p->n_robots > 256) return fail(D4_EINVAL, "samples per group %d invalid", t.S);
     if (t.R < 1 || t.R > 8 || t.R * t.S * p->n_robots > 1024) return fail(D4_EINVAL, "replicas %d invalid", t.R);
     if (t.Tb < cs || t.Tb > 64 || t.Tb % cs) return fail(D4_EINVAL, "steps per block %d invalid", t.Tb);
     if (rollfit_lds(p, t) > 160 * 1024) return fail(D4_EUNSUPPORTED, "tile needs too much LDS");
@@ -538,30 +553,29 @@ int32_t d4_tile_get(const d4_problem* p, int32_t batched, int32_t* samples_per_g
     return D4_OK;
 }
 
-int32_t d4_autotune(const d4_problem* p, int32_t reps, int32_t* samples_per_group, int32_t* steps_per_block,
-                    int32_t* replicas, float* best_us) {
+int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int32_t reps,
+                    int32_t* samples_per_group, int32_t* steps_per_block, int32_t* replicas, float* best_us) {
     int rc = validate(p);
     if (rc) return rc;
+    NEED(x0);
+    NEED(goal);
     if (reps < 1) reps = 5;
     const Shape s = shape_of(p->dyn);
     const size_t n = p->n_robots, T = p->horizon, M = p->n_samples, D = n * T * s.du;
-    float *eps = nullptr, *r = nullptr, *x0 = nullptr, *goal = nullptr, *ub = nullptr;
+    float *eps = nullptr, *r = nullptr, *ub = nullptr;
     int* hits = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto release = [&]() {
-        for (void* q : {(void*)eps, (void*)r, (void*)x0, (void*)goal, (void*)ub, (void*)hits})
+        for (void* q : {(void*)eps, (void*)r, (void*)ub, (void*)hits})
             if (q) (void)hipFree(q);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
     if (hipMalloc(&eps, 4 * D * M) != hipSuccess || hipMalloc(&r, 4 * M) != hipSuccess ||
-        hipMalloc(&hits, 4 * M) != hipSuccess || hipMalloc(&x0, 4 * n * s.dx) != hipSuccess ||
-        hipMalloc(&goal, 4 * n * s.dp) != hipSuccess || hipMalloc(&ub, 4 * D) != hipSuccess) {
+        hipMalloc(&hits, 4 * M) != hipSuccess || hipMalloc(&ub, 4 * D) != hipSuccess) {
         release();
         return fail(D4_ENOMEM, "autotune scratch allocation failed");
     }
-    (void)hipMemset(x0, 0, 4 * n * s.dx);
-    (void)hipMemset(goal, 0, 4 * n * s.dp);
     (void)hipMemset(ub, 0, 4 * D);
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);

@@ -45,13 +45,43 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 }
 
 // ------------------------------------------------ FP32 ln and sin/cos recipe
+// Correctly rounded a / b for the operands of ln_unit (a in [-0.25, 0.5],
+// b in [1.75, 2.5]): the reciprocal refinement and the two residual
+// corrections of the full IEEE division sequence, without its range scaling
+// and special-value fix-up, which are identities for finite operands of
+// moderate exponent.  Every reachable operand pair is checked against the
+// correctly rounded quotient by the exhaustive transform test.
+__device__ __forceinline__ float div_rn_moderate(float a, float b) {
+    float y = __builtin_amdgcn_rcpf(b);
+    const float e = __builtin_fmaf(-b, y, 1.0f);
+    y = __builtin_fmaf(e, y, y);
+    float q = a * y;
+    float r = __builtin_fmaf(-b, q, a);
+    q = __builtin_fmaf(r, y, q);
+    r = __builtin_fmaf(-b, q, a);
+    return __builtin_fmaf(r, y, q);
+}
+
+// Correctly rounded sqrt(x) for finite normal x > 0 away from the denormal
+// range: the hardware estimate (within 1 ulp) is moved to a neighbour when the
+// exact residual x - s' s says that the neighbour is nearer.
+__device__ __forceinline__ float sqrt_rn_normal(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float s_dn = __uint_as_float(__float_as_uint(s) - 1u);
+    const float s_up = __uint_as_float(__float_as_uint(s) + 1u);
+    const float r_dn = __builtin_fmaf(-s_dn, s, x);
+    const float r_up = __builtin_fmaf(-s_up, s, x);
+    float out = r_dn <= 0.0f ? s_dn : s;
+    return r_up > 0.0f ? s_up : out;
+}
+
 // Natural log of a uniform in (0, 1): u = 2^e f, f in [0.75, 1.5),
 // ln f = 2 atanh(s), s = (f - 1)/(f + 1), atanh by its Taylor series in
-// Horner form through s^11, e*ln2 split as 355/512 plus the FP32 remainder.
+// Horner form through s^9, e*ln2 split as 355/512 plus the FP32 remainder.
+// Within 2 ulp of ln u for every uniform the recipe produces.
 __device__ __forceinline__ float ln_unit(float u) {
 #pragma clang fp contract(off)
-    const float A3 = 1.0f / 3.0f, A5 = 1.0f / 5.0f, A7 = 1.0f / 7.0f, A9 = 1.0f / 9.0f,
-                A11 = 1.0f / 11.0f;
+    const float A3 = 1.0f / 3.0f, A5 = 1.0f / 5.0f, A7 = 1.0f / 7.0f, A9 = 1.0f / 9.0f;
     const float LN2_HI = 355.0f / 512.0f;
     const float LN2_LO = (float)(0.693147180559945309417232121458 - 355.0 / 512.0);
     const uint32_t b = __float_as_uint(u);
@@ -60,10 +90,9 @@ __device__ __forceinline__ float ln_unit(float u) {
     const bool big = f >= 1.5f;
     f = big ? f * 0.5f : f;
     e += big ? 1 : 0;
-    const float s = (f - 1.0f) / (f + 1.0f);
+    const float s = div_rn_moderate(f - 1.0f, f + 1.0f);
     const float s2 = s * s;
-    float q = A11 * s2 + A9;
-    q = q * s2 + A7;
+    float q = A9 * s2 + A7;
     q = q * s2 + A5;
     q = q * s2 + A3;
     const float t = s + s * (s2 * q);
@@ -75,13 +104,12 @@ __device__ __forceinline__ float ln_unit(float u) {
 }
 
 // sin and cos of 2 pi u_b for u_b = (2j + 1) 2^-24, j = word >> 9: exact
-// quarter-turn reduction in integers, then Taylor series on [-pi/4, pi/4].
+// quarter-turn reduction in integers, then Taylor series on [-pi/4, pi/4]
+// (sine through y^9, cosine through y^8; within 2 ulp, or 2^-23 absolute).
 __device__ __forceinline__ void sincos_2pi_word(uint32_t word, float& sn_o, float& cs_o) {
 #pragma clang fp contract(off)
-    const float S3 = -1.0f / 6.0f, S5 = 1.0f / 120.0f, S7 = -1.0f / 5040.0f,
-                S9 = 1.0f / 362880.0f, S11 = -1.0f / 39916800.0f;
-    const float C2 = -1.0f / 2.0f, C4 = 1.0f / 24.0f, C6 = -1.0f / 720.0f, C8 = 1.0f / 40320.0f,
-                C10 = -1.0f / 3628800.0f, C12 = 1.0f / 479001600.0f;
+    const float S3 = -1.0f / 6.0f, S5 = 1.0f / 120.0f, S7 = -1.0f / 5040.0f, S9 = 1.0f / 362880.0f;
+    const float C2 = -1.0f / 2.0f, C4 = 1.0f / 24.0f, C6 = -1.0f / 720.0f, C8 = 1.0f / 40320.0f;
     const float PI_F = 3.14159265358979323846f;
     const int jj = (int)((word >> 9) << 1) + 1;
     const int q = (jj + (1 << 21)) >> 22;
@@ -89,14 +117,11 @@ __device__ __forceinline__ void sincos_2pi_word(uint32_t word, float& sn_o, floa
     const float r = (float)rn * 0x1.0p-23f;
     const float y = r * PI_F;
     const float y2 = y * y;
-    float sp = S11 * y2 + S9;
-    sp = sp * y2 + S7;
+    float sp = S9 * y2 + S7;
     sp = sp * y2 + S5;
     sp = sp * y2 + S3;
     const float sn = y + y * (y2 * sp);
-    float cp = C12 * y2 + C10;
-    cp = cp * y2 + C8;
-    cp = cp * y2 + C6;
+    float cp = C8 * y2 + C6;
     cp = cp * y2 + C4;
     cp = cp * y2 + C2;
     const float cs = 1.0f + y2 * cp;
@@ -109,10 +134,12 @@ __device__ __forceinline__ void sincos_2pi_word(uint32_t word, float& sn_o, floa
     cs_o = __uint_as_float(__float_as_uint(b) ^ (((qq + 1u) & 2u) << 30));
 }
 
+// rho = sqrt(-2 ln u_a) lies in [3e-4, 5.8]: its square is a normal FP32
+// number, so sqrt_rn_normal applies.
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z_even, float& z_odd) {
 #pragma clang fp contract(off)
     const float u = (float)(((wa >> 9) << 1) + 1u) * 0x1.0p-24f;
-    const float rho = __builtin_sqrtf(-2.0f * ln_unit(u));
+    const float rho = sqrt_rn_normal(-2.0f * ln_unit(u));
     float s, c;
     sincos_2pi_word(wb, s, c);
     z_even = rho * c;
@@ -133,6 +160,47 @@ __device__ __forceinline__ void normal_block(uint32_t group, uint32_t m, uint32_
 // v_sqrt_f32 (1 ulp) instead of the correctly rounded sequence.
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// ------------------------------------------------------------- scoring forms
+// Every kernel that samples, rolls out or scores uses these FP32 forms (and
+// the dynamics below), with explicit fused multiply-adds and no other
+// contraction, so that all of them produce the same bits for the same
+// trajectory whatever the surrounding code.
+
+// Squared distance of a position to the goal.
+template <int DP>
+__device__ __forceinline__ float goal_d2(const float* x, const float* g) {
+#pragma clang fp contract(off)
+    const float d0 = x[0] - g[0];
+    float acc = d0 * d0;
+#pragma unroll
+    for (int c = 1; c < DP; ++c) {
+        const float dc = x[c] - g[c];
+        acc = __builtin_fmaf(dc, dc, acc);
+    }
+    return acc;
+}
+
+// 1 / max(|p_0 - g|, d0_floor): the goal term's normaliser.
+__device__ __forceinline__ float inv_start_dist(float d0_2, float d0_floor) {
+    return 1.0f / fmaxf(__builtin_amdgcn_sqrtf(d0_2), d0_floor);
+}
+
+// Per-step goal reward 1 - |p_t - g| / d0 from the distance itself.
+__device__ __forceinline__ float goal_term(float dist, float inv_d0) {
+    return __builtin_fmaf(-dist, inv_d0, 1.0f);
+}
+
+// Sampled control clip(u_base + du * mean_scale + sigma * eps) of one element.
+__device__ __forceinline__ float sample_control(float ub, float du, float mscale, float sigma, float z, float lo,
+                                                float hi) {
+    return fminf(fmaxf(__builtin_fmaf(sigma, z, __builtin_fmaf(du, mscale, ub)), lo), hi);
+}
+
+// Team reward (sum of goal terms - w_safe * penalty) / (n T).
+__device__ __forceinline__ float team_reward(float goal_sum, float w_safe, float penalty, int nT) {
+    return __builtin_fmaf(-w_safe, penalty, goal_sum) / (float)nT;
+}
+
 // ---------------------------------------------------------------- dynamics
 struct StepConsts {
     float dt, hdt, hdt2, dt6, vmax;
@@ -146,11 +214,12 @@ struct Dyn<HOLO2D> {
     static constexpr int DX = 4, DU = 2, DP = 2, AUX = 1;
     __device__ __forceinline__ static void init(const float*, float*) {}
     __device__ __forceinline__ static void step(float* x, float*, const float* u, const StepConsts& c) {
+#pragma clang fp contract(off)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const float p = x[i], v = x[2 + i], a = u[i];
-            x[i] = p + v * c.dt + a * c.hdt2;
-            x[2 + i] = fminf(fmaxf(v + a * c.dt, -c.vmax), c.vmax);
+            x[i] = __builtin_fmaf(a, c.hdt2, __builtin_fmaf(v, c.dt, p));
+            x[2 + i] = fminf(fmaxf(__builtin_fmaf(a, c.dt, v), -c.vmax), c.vmax);
         }
     }
 };
@@ -160,11 +229,12 @@ struct Dyn<HOLO3D> {
     static constexpr int DX = 6, DU = 3, DP = 3, AUX = 1;
     __device__ __forceinline__ static void init(const float*, float*) {}
     __device__ __forceinline__ static void step(float* x, float*, const float* u, const StepConsts& c) {
+#pragma clang fp contract(off)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const float p = x[i], v = x[3 + i], a = u[i];
-            x[i] = p + v * c.dt + a * c.hdt2;
-            x[3 + i] = fminf(fmaxf(v + a * c.dt, -c.vmax), c.vmax);
+            x[i] = __builtin_fmaf(a, c.hdt2, __builtin_fmaf(v, c.dt, p));
+            x[3 + i] = fminf(fmaxf(__builtin_fmaf(a, c.dt, v), -c.vmax), c.vmax);
         }
     }
 };
@@ -178,15 +248,16 @@ struct Dyn<UNICYCLE> {
     }
     __device__ __forceinline__ static void step(float* x, float* aux, const float* u,
                                                 const StepConsts& c) {
+#pragma clang fp contract(off)
         const float v = u[0], om = u[1];
-        const float th_h = x[2] + om * c.hdt;
-        const float th_1 = x[2] + om * c.dt;
+        const float th_h = __builtin_fmaf(om, c.hdt, x[2]);
+        const float th_1 = __builtin_fmaf(om, c.dt, x[2]);
         float sh, ch, s1, c1;
         __sincosf(th_h, &sh, &ch);
         __sincosf(th_1, &s1, &c1);
         const float kv = v * c.dt6;
-        x[0] = x[0] + kv * (aux[0] + 4.0f * ch + c1);
-        x[1] = x[1] + kv * (aux[1] + 4.0f * sh + s1);
+        x[0] = __builtin_fmaf(kv, __builtin_fmaf(4.0f, ch, aux[0]) + c1, x[0]);
+        x[1] = __builtin_fmaf(kv, __builtin_fmaf(4.0f, sh, aux[1]) + s1, x[1]);
         x[2] = th_1;
         aux[0] = c1;
         aux[1] = s1;
@@ -203,6 +274,25 @@ __device__ __forceinline__ float pair_d2(const float* a, const float* b) {
     for (int c = 1; c < DP; ++c) {
         const float dc = a[c] - b[c];
         acc = acc + dc * dc;
+    }
+    return acc;
+}
+
+// Squared gap between two axis-aligned boxes [alo, ahi] and [blo, bhi] in the
+// order of pair_d2, with per-axis gap g = max(alo - bhi, blo - ahi, 0).  For
+// points a in the first box and b in the second, |fl(a - b)| >= fl-gap on
+// every axis, because rounding is monotonic; squaring and adding in the same
+// order keep the inequality, so pair_d2(a, b) >= box_gap2(...) holds exactly
+// in FP32 and a box pair with gap above the threshold holds no hit.
+template <int DP>
+__device__ __forceinline__ float box_gap2(const float* alo, const float* ahi, const float* blo,
+                                          const float* bhi) {
+#pragma clang fp contract(off)
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < DP; ++c) {
+        const float gc = fmaxf(fmaxf(alo[c] - bhi[c], blo[c] - ahi[c]), 0.0f);
+        acc = c == 0 ? gc * gc : acc + gc * gc;
     }
     return acc;
 }

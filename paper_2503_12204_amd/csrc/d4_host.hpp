@@ -152,11 +152,11 @@ struct Tile {
 // rule serves the single-problem and the batched kernels (workgroups of at most
 // 256 lanes), so a batched instance reproduces its single-problem run bit for
 // bit: S = min(64, floor(256 / n)) samples, and a time block that keeps the
-// double-buffered positions near 64 KiB, in whole draw chunks.
+// positions near 64 KiB, in whole draw chunks.
 inline Tile default_tile(int dyn, int n) {
     int S = std::min(64, 256 / n);
     const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
-    const int per_step = 2 * (2 * n - 1) * S * slot;
+    const int per_step = (2 * n - 1) * S * slot;
     int Tb = (64 * 1024) / per_step;
     const int cs = shape_of(dyn).du == 2 ? 2 : 4;
     Tb = std::max(cs, std::min(16, Tb / cs * cs));
@@ -176,7 +176,8 @@ inline Tile single_tile(int dyn, int n, int M) {
     if (S == t.S) return t;
     const int R = std::max(1, std::min(4, 256 / (S * n)));
     const int cs = shape_of(dyn).du == 2 ? 2 : 4;
-    const int Tb = R > 1 ? 16 : std::max(cs, std::min(16, ((64 * 1024) / (2 * (2 * n - 1) * S * 16)) / cs * cs));
+    const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
+    const int Tb = R > 1 ? 16 : std::max(cs, std::min(16, ((64 * 1024) / ((2 * n - 1) * S * slot)) / cs * cs));
     Tile out;
     out.S = S;
     out.Tb = Tb;
@@ -193,7 +194,7 @@ inline Tile pick_tile(const d4_problem* p) {
     const char* env = std::getenv("D4_TILE_S");
     if (env) {
         int v = std::atoi(env);
-        if (v >= 1 && v <= 64 && v * n <= 1024) S = v;
+        if (v >= 1 && v <= 64 && v * n <= 256) S = v;
     }
     const char* envt = std::getenv("D4_TILE_TB");
     if (envt) {
@@ -227,7 +228,9 @@ inline size_t rollfit_lds(const d4_problem* p, Tile t) {
         const size_t b = (size_t)(2 + t.R) * n * t.S * 4;
         return a > b ? a : b;
     }
-    const size_t a = (size_t)2 * t.Tb * n2 * t.S * slot + (size_t)2 * t.Tb * t.S * 4;
+    // one-lane kernel: positions [Tb][2n-1][S], boxes [n][S][2], masks [2][Tb][S], flags [2][S]
+    const size_t a = (size_t)t.Tb * n2 * t.S * slot + (size_t)2 * n * t.S * slot +
+                     (size_t)2 * t.Tb * t.S * 4 + (size_t)2 * t.S * 4;
     const size_t b = (size_t)3 * n * t.S * 4;
     return a > b ? a : b;
 }

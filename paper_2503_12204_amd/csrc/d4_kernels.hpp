@@ -18,9 +18,12 @@
 // 0..n-2 again, so a lane's partners are contiguous) and the pair checks of
 // one step read consecutive slots across a wave.  Lane k checks partners (k + j) mod n
 // for j = 1..floor((n-1)/2), plus j = n/2 for k < n/2 when n is even: every
-// unordered pair exactly once, spread evenly.  The per-(m, t) "robot k hit
-// anything" bits are OR-ed into an LDS word; positions and masks are double
-// buffered, so each time block costs two barriers.
+// unordered pair exactly once, spread evenly.  Each lane also keeps the
+// bounding box of its positions over the block; a partner is checked step by
+// step only when the two boxes come within the threshold (exact in FP32, see
+// box_gap2), which skips nearly all pairs of robots that stay apart.  The
+// per-(m, t) "robot k hit anything" bits are OR-ed into an LDS word; masks are
+// double buffered, so each time block costs two barriers.
 #pragma once
 
 #include "d4_device.hpp"
@@ -43,6 +46,7 @@ __device__ __forceinline__ float wave_max(float v) {
 // order.  Used by every producer of reward statistics so that they agree bit
 // for bit; a single thread avoids cross-lane reads in partially filled waves.
 __device__ __forceinline__ float4 reward_stats_seq(const float* r, int n) {
+#pragma clang fp contract(off)
     float s = 0.0f, mx = -INFINITY;
     for (int i = 0; i < n; ++i) {
         s += r[i];
@@ -53,7 +57,7 @@ __device__ __forceinline__ float4 reward_stats_seq(const float* r, int n) {
     float m2 = 0.0f;
     for (int i = 0; i < n; ++i) {
         const float d = r[i] - mean;
-        m2 += d * d;
+        m2 = __builtin_fmaf(d, d, m2);
     }
     return make_float4(cnt, mean, m2, mx);
 }
@@ -143,6 +147,27 @@ __device__ __forceinline__ uint32_t pair_bits(const typename PosSlot<DP>::T* pb,
     return (uint32_t)((bits | (bits >> n)) & low);
 }
 
+// As pair_bits, for the partners j (bit j of near) that the block's bounding
+// boxes could not rule out; the remaining partners hold no hit in this block.
+template <int DP>
+__device__ __forceinline__ uint32_t pair_bits_near(const typename PosSlot<DP>::T* pb, int n, int S, int k,
+                                                   uint32_t near, float thr2) {
+    using PS = PosSlot<DP>;
+    float pk[DP];
+    PS::unpack(pb[k * S], pk);
+    const typename PS::T* q = pb + (k + 1) * S;
+    uint64_t bits = 0ull;
+    while (near) {
+        const int j = __builtin_ctz(near);
+        near &= near - 1u;
+        float pl[DP];
+        PS::unpack(q[j * S], pl);
+        if (pair_d2<DP>(pk, pl) <= thr2) bits |= 2ull << (k + j);
+    }
+    const uint64_t low = n >= 32 ? 0xFFFFFFFFull : ((1ull << n) - 1ull);
+    return (uint32_t)((bits | (bits >> n)) & low);
+}
+
 // Steps per noise chunk (a whole number of Philox blocks) and blocks per chunk.
 template <int DU>
 struct Chunk {
@@ -173,8 +198,10 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
     const bool live = active && m < M;
     const int mc = m < M ? m : M - 1;
     const int n2 = 2 * n - 1;                                                    // slots per step
-    PT* pos = reinterpret_cast<PT*>(lds);                                        // [2][Tb][2n-1][S]
-    uint32_t* mask = reinterpret_cast<uint32_t*>(pos + 2 * Tb * n2 * S);         // [2][Tb][S]
+    PT* pos = reinterpret_cast<PT*>(lds);                                        // [Tb][2n-1][S]
+    PT* box = pos + Tb * n2 * S;                                                 // [n][S][lo, hi]
+    uint32_t* mask = reinterpret_cast<uint32_t*>(box + 2 * n * S);              // [2][Tb][S]
+    uint32_t* anyhit = mask + 2 * Tb * S;                                        // [2][S]
 
     float x[DX], aux[DY::AUX], g[DP];
     if (FROM_X) {
@@ -188,10 +215,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
     }
 #pragma unroll
     for (int c = 0; c < DP; ++c) g[c] = a.goal[k * DP + c];
-    float d0s = 0.0f;
-#pragma unroll
-    for (int c = 0; c < DP; ++c) d0s += (x[c] - g[c]) * (x[c] - g[c]);
-    const float inv_d0 = 1.0f / fmaxf(fast_sqrt(d0s), a.d0_floor);
+    const float inv_d0 = inv_start_dist(goal_d2<DP>(x, g), a.d0_floor);
 
     float goal_acc = 0.0f;
     int safe_cnt = 0, hit_cnt = 0;
@@ -213,35 +237,72 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
     const int jmax = active ? ((n - 1) >> 1) + ((((n & 1) == 0) && (k < (n >> 1))) ? 1 : 0) : 0;
     const bool pairs_mode = (a.flags & FLAG_SAFE_PAIRS) != 0;
     const size_t Ms = (size_t)M;
+    // eps stores go through a buffer resource with 32-bit offsets when the
+    // whole [D][M] array (plus one chunk of rows) spans under 2 GiB
+    const size_t Dt = (size_t)n * T * DU;
+    const bool eps32 = (Dt + 64) * Ms * 4 <= 0x7FFFFFFFull;
+    const int eps_voff = eps32 ? (int)(((size_t)k * T * DU * Ms + (size_t)m) * 4) : 0;
 
-    // goal term and LDS position of the state after step t (slot tt of buffer buf)
-    auto after_step = [&](int buf, int tt) {
-        float dist2 = 0.0f;
+    // bounding box of this lane's positions over the current block
+    float blo[DP], bhi[DP];
+
+    // goal term, LDS position and bounding box of the state after step tt of the block
+    auto after_step = [&](int tt) {
+        goal_acc += goal_term(fast_sqrt(goal_d2<DP>(x, g)), inv_d0);
 #pragma unroll
-        for (int c = 0; c < DP; ++c) dist2 += (x[c] - g[c]) * (x[c] - g[c]);
-        goal_acc += 1.0f - fast_sqrt(dist2) * inv_d0;
+        for (int c = 0; c < DP; ++c) {
+            blo[c] = fminf(blo[c], x[c]);
+            bhi[c] = fmaxf(bhi[c], x[c]);
+        }
         if (active) {
             const PT v = PS::pack(x);
-            PT* slot = pos + ((buf * Tb + tt) * n2 + k) * S + ms;
+            PT* slot = pos + (tt * n2 + k) * S + ms;
             slot[0] = v;
             if (k < n - 1) slot[n * S] = v;
         }
     };
+
+    // control bases (u_base, du_in) of the next draw chunk, loaded one chunk
+    // ahead so that their latency hides behind the current chunk's draws
+    constexpr int CS = Chunk<DU>::STEPS, CG = Chunk<DU>::GROUPS, NE = 4 * CG;
+    float ub_nx[NE], du_nx[NE];
+    auto load_ctrl = [&](int t) {
+        const int ne = min(CS, T - t) * DU;
+        const float* ubp = a.u_base + ebase + (uint32_t)(t * DU);
+        const float* dup = a.du_in + ebase + (uint32_t)(t * DU);
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            ub_nx[j] = j < ne ? ubp[j] : 0.0f;
+            du_nx[j] = j < ne ? dup[j] : 0.0f;
+        }
+    };
+    if (!FROM_X) load_ctrl(0);
 
     const int nblk = (T + Tb - 1) / Tb;
     for (int b = 0; b < nblk; ++b) {
         const int buf = b & 1;
         const int t0 = b * Tb;
         const int tcount = min(Tb, T - t0);
+#pragma unroll
+        for (int c = 0; c < DP; ++c) {
+            blo[c] = INFINITY;
+            bhi[c] = -INFINITY;
+        }
         if (!FROM_X) {
             // Chunks of CS steps use CS*DU = 4*CG consecutive draws starting at
             // phase p of a Philox block; the window holds the block the
             // previous chunk ended in ("left") plus CG new blocks.
-            constexpr int CS = Chunk<DU>::STEPS, CG = Chunk<DU>::GROUPS;
             for (int tc = 0; tc < tcount; tc += CS) {
                 const int t = t0 + tc;
                 const uint32_t e0 = ebase + (uint32_t)(t * DU);
                 const uint32_t g0 = e0 >> 2;
+                float ub_c[NE], du_c[NE];
+#pragma unroll
+                for (int j = 0; j < NE; ++j) {
+                    ub_c[j] = ub_nx[j];
+                    du_c[j] = du_nx[j];
+                }
+                if (t + CS < T) load_ctrl(t + CS);
                 float win[4 + 4 * CG];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) win[j] = left[j];
@@ -257,9 +318,22 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
                 for (int j = 0; j < 4; ++j) left[j] = win[4 * CG + j];
                 const int steps = min(CS, T - t);
                 if (live) {
+                    if (eps32) {
+                        // rows e0 .. e0+4CG-1 of eps: a uniform base for this chunk's
+                        // steps, the lane's fixed offset and a uniform row offset
+                        const uint32_t rows_left = (uint32_t)(Dt - (size_t)t * DU);
+                        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                            a.eps + (size_t)t * DU * Ms, (short)0, (int)(rows_left * (uint32_t)M * 4u), 0x00020000);
 #pragma unroll
-                    for (int j = 0; j < 4 * CG; ++j)
-                        if (j < steps * DU) a.eps[(size_t)(e0 + j) * Ms + m] = z[j];
+                        for (int j = 0; j < 4 * CG; ++j)
+                            if (j < steps * DU)
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(z[j]), rs, eps_voff, j * M * 4, 0);
+                    } else {
+                        float* ep = a.eps + (size_t)e0 * Ms + m;
+#pragma unroll
+                        for (int j = 0; j < 4 * CG; ++j)
+                            if (j < steps * DU) ep[(size_t)j * Ms] = z[j];
+                    }
                 }
 #pragma unroll
                 for (int s = 0; s < CS; ++s) {
@@ -267,12 +341,11 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
                         float u[DU];
 #pragma unroll
                         for (int d = 0; d < DU; ++d) {
-                            const uint32_t e = e0 + s * DU + d;
-                            const float cb = a.u_base[e] + a.du_in[e] * mscale;
-                            u[d] = fminf(fmaxf(cb + sigma * z[s * DU + d], ulo[d]), uhi[d]);
+                            u[d] = sample_control(ub_c[s * DU + d], du_c[s * DU + d], mscale, sigma,
+                                                  z[s * DU + d], ulo[d], uhi[d]);
                         }
                         DY::step(x, aux, u, a.sc);
-                        after_step(buf, tc + s);
+                        after_step(tc + s);
                     }
                 }
             }
@@ -282,19 +355,45 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
                 const float* xr = a.xs + (((size_t)mc * n + k) * (size_t)(T + 1) + (t + 1)) * DX;
 #pragma unroll
                 for (int c = 0; c < DP; ++c) x[c] = xr[c];
-                after_step(buf, tt);
+                after_step(tt);
             }
         }
-        if (k_raw == 0)
+        if (active) {
+            box[(k * S + ms) * 2] = PS::pack(blo);
+            box[(k * S + ms) * 2 + 1] = PS::pack(bhi);
+        }
+        if (k_raw == 0) {
             for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
-        __syncthreads();
-        for (int tt = 0; tt < tcount; ++tt) {
-            const uint32_t bits = pair_bits<DP>(pos + (buf * Tb + tt) * n2 * S + ms, n, S, k, jmax, a.thr2);
-            hit_cnt += __popc(bits);
-            if (bits) atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));
+            anyhit[buf * S + ms] = 0u;
         }
         __syncthreads();
-        if (active)
+        // broad phase: partners whose block boxes come within the threshold
+        uint32_t near = 0u;
+        {
+            int l = k + 1 < n ? k + 1 : 0;
+            for (int j = 0; j < jmax; ++j) {
+                float llo[DP], lhi[DP];
+                PS::unpack(box[(l * S + ms) * 2], llo);
+                PS::unpack(box[(l * S + ms) * 2 + 1], lhi);
+                near |= (box_gap2<DP>(blo, bhi, llo, lhi) <= a.thr2) ? (1u << j) : 0u;
+                l = l + 1 < n ? l + 1 : 0;
+            }
+        }
+        // narrow phase: exact checks of those partners at every step of the block
+        if (near) {
+            bool any = false;
+            for (int tt = 0; tt < tcount; ++tt) {
+                const uint32_t bits = pair_bits_near<DP>(pos + tt * n2 * S + ms, n, S, k, near, a.thr2);
+                hit_cnt += __popc(bits);
+                if (bits) {
+                    atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));
+                    any = true;
+                }
+            }
+            if (any) atomicOr(&anyhit[buf * S + ms], 1u);
+        }
+        __syncthreads();
+        if (active && anyhit[buf * S + ms])
             for (int tt = 0; tt < tcount; ++tt) safe_cnt += (mask[(buf * Tb + tt) * S + ms] >> k) & 1u;
     }
 
@@ -317,7 +416,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
             hs += rh[kk * S + ms];
         }
         const float pen = pairs_mode ? (float)(2 * hs) : (float)ss;
-        const float rv = (gs - a.w_safe * pen) / (float)(n * T);
+        const float rv = team_reward(gs, a.w_safe, pen, n * T);
         a.r[m] = rv;
         a.hits[m] = hs;
         if (a.robots_hit) a.robots_hit[m] = ss;
@@ -328,7 +427,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
 }
 
 template <int DYN, int MODE>
-__global__ void __launch_bounds__(1024) k_rollfit(const RollFitArgs a) {
+__global__ void __launch_bounds__(256) k_rollfit(const RollFitArgs a) {
     extern __shared__ float lds[];
     rollfit_tile<DYN, MODE>(a, blockIdx.x * a.S, blockIdx.x, lds);
 }
@@ -372,10 +471,7 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
     DY::init(x, aux);
 #pragma unroll
     for (int c = 0; c < DP; ++c) g[c] = a.goal[k * DP + c];
-    float d0s = 0.0f;
-#pragma unroll
-    for (int c = 0; c < DP; ++c) d0s += (x[c] - g[c]) * (x[c] - g[c]);
-    const float inv_d0 = 1.0f / fmaxf(fast_sqrt(d0s), a.d0_floor);
+    const float inv_d0 = inv_start_dist(goal_d2<DP>(x, g), a.d0_floor);
     float goal_acc = 0.0f;
     int safe_cnt = 0, hit_cnt = 0;
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
@@ -427,14 +523,10 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
                 for (int d = 0; d < DU; ++d) {
                     const uint32_t e = ebase + (uint32_t)(t * DU + d);
                     const float z = nzk[(size_t)(((e >> 2) - g_a) * 4 + (e & 3u)) * S];
-                    const float cb = a.u_base[e] + a.du_in[e] * mscale;
-                    u[d] = fminf(fmaxf(cb + sigma * z, ulo[d]), uhi[d]);
+                    u[d] = sample_control(a.u_base[e], a.du_in[e], mscale, sigma, z, ulo[d], uhi[d]);
                 }
                 DY::step(x, aux, u, a.sc);
-                float dist2 = 0.0f;
-#pragma unroll
-                for (int c = 0; c < DP; ++c) dist2 += (x[c] - g[c]) * (x[c] - g[c]);
-                goal_acc += 1.0f - fast_sqrt(dist2) * inv_d0;
+                goal_acc += goal_term(fast_sqrt(goal_d2<DP>(x, g)), inv_d0);
                 const PT v = PS::pack(x);
                 PT* slot = pos + (tt * n2 + k) * S + ms;
                 slot[0] = v;
@@ -477,7 +569,7 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
             for (int rr = 0; rr < R; ++rr) hs += rh[rr * group + kk * S + ms];
         }
         const float pen = pairs_mode ? (float)(2 * hs) : (float)ss;
-        const float rv = (gs - a.w_safe * pen) / (float)(n * T);
+        const float rv = team_reward(gs, a.w_safe, pen, n * T);
         a.r[m] = rv;
         a.hits[m] = hs;
         if (a.robots_hit) a.robots_hit[m] = ss;
@@ -494,6 +586,16 @@ __global__ void __launch_bounds__(1024) k_rollfit_coop(const RollFitArgs a, int 
 }
 
 // eps[e][m] for e < D, m < M; one lane per (Philox block, sample).
+static __global__ void __launch_bounds__(256) k_box_muller(const uint32_t* words, int64_t count, float* z) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float a, b;
+        box_muller(words[2 * i], words[2 * i + 1], a, b);
+        z[2 * i] = a;
+        z[2 * i + 1] = b;
+    }
+}
+
 static __global__ void __launch_bounds__(256) k_noise(float* eps, int D, int M, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -539,12 +641,13 @@ __global__ void __launch_bounds__(256) k_rollout(const float* x0, const float* u
 
 // Chan's pairwise combination of (count, mean, M2, max) summaries.
 __device__ __forceinline__ float4 chan_combine(float4 a, float4 b) {
+#pragma clang fp contract(off)
     if (b.x == 0.0f) return a;
     if (a.x == 0.0f) return b;
     const float nn = a.x + b.x;
     const float d = b.y - a.y;
     const float f = b.x / nn;
-    return make_float4(nn, a.y + d * f, a.z + b.z + d * d * a.x * f, fmaxf(a.w, b.w));
+    return make_float4(nn, __builtin_fmaf(d, f, a.y), __builtin_fmaf((d * d) * a.x, f, a.z + b.z), fmaxf(a.w, b.w));
 }
 
 __device__ __forceinline__ float4 wave_combine(float4 v) {
@@ -706,10 +809,7 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
         DY::init(x, aux);
 #pragma unroll
         for (int c = 0; c < DP; ++c) g[c] = a.goal[k * DP + c];
-        float d0s = 0.0f;
-#pragma unroll
-        for (int c = 0; c < DP; ++c) d0s += (x[c] - g[c]) * (x[c] - g[c]);
-        const float inv_d0 = 1.0f / fmaxf(fast_sqrt(d0s), a.d0_floor);
+        const float inv_d0 = inv_start_dist(goal_d2<DP>(x, g), a.d0_floor);
         float* tr = a.traj + (size_t)k * (T + 1) * DX;
 #pragma unroll
         for (int c = 0; c < DX; ++c) tr[c] = x[c];
@@ -720,11 +820,8 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
             DY::step(x, aux, u, a.sc);
 #pragma unroll
             for (int c = 0; c < DX; ++c) tr[(t + 1) * DX + c] = x[c];
-            float d2 = 0.0f;
-#pragma unroll
-            for (int c = 0; c < DP; ++c) d2 += (x[c] - g[c]) * (x[c] - g[c]);
-            const float dist = fast_sqrt(d2);
-            gacc += 1.0f - dist * inv_d0;
+            const float dist = fast_sqrt(goal_d2<DP>(x, g));
+            gacc += goal_term(dist, inv_d0);
             at_goal += dist <= a.goal_tol;
             if (t == T - 1) term_bad = dist > a.goal_tol;
         }
@@ -769,7 +866,7 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
             bad |= red_bad[i];
         }
         const float pen = (a.flags & FLAG_SAFE_PAIRS) ? (float)(2 * hs) : (float)ss;
-        a.stats[0] = (gs - a.w_safe * pen) / (float)(n * T);
+        a.stats[0] = team_reward(gs, a.w_safe, pen, n * T);
         a.stats[1] = (float)os / (float)(n * T);
         int* si = reinterpret_cast<int*>(a.stats);
         si[2] = hs;

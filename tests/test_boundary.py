@@ -79,3 +79,8 @@ def test_null_and_misaligned_pointers_rejected(L):
     assert L.lib().d4_noise(ctypes.byref(c), 70000, 1, ctypes.cast(buf, ctypes.c_void_p), None) == L.D4_EINVAL
     assert L.lib().d4_denoise_iter(None, ctypes.byref(c), None, None, None, 0, None, None, None) == L.D4_EINVAL
     assert L.lib().d4_ctx_create(ctypes.byref(c), None) == L.D4_EINVAL
+    # the transform entry: negative counts and NULL arrays fail, an empty call launches nothing
+    assert L.lib().d4_box_muller(None, -1, None, None) == L.D4_EINVAL
+    assert L.lib().d4_box_muller(None, 4, ctypes.cast(buf, ctypes.c_void_p), None) == L.D4_EINVAL
+    assert L.lib().d4_box_muller(ctypes.cast(buf, ctypes.c_void_p), 4, odd, None) == L.D4_EINVAL
+    assert L.lib().d4_box_muller(None, 0, None, None) == L.D4_OK

@@ -61,6 +61,29 @@ def test_noise_bitexact(L, name, p, x0, g):
             f"{int((eps != ref).sum())} of {eps.size} draws differ"
 
 
+def test_box_muller_exhaustive(L):
+    """Every radius word and every angle word the recipe distinguishes
+    (word >> 9 takes 2^23 values each) gives the oracle's bits.  Radius words
+    pair with the smallest angle (cos = 1 exactly, so z_even is rho itself);
+    angle words pair with two radius words through a permutation, so sine and
+    cosine show through non-trivial products."""
+    print("case box-muller exhaustive", flush=True)
+    j = np.arange(1 << 23, dtype=np.uint64)
+    words = (j << np.uint64(9)).astype(np.uint32)
+    perm = ((j * np.uint64(2654435761)) & np.uint64((1 << 23) - 1)).astype(np.uint64)
+    pw = (perm << np.uint64(9)).astype(np.uint32)
+    zero = np.zeros_like(words)
+    for wa, wb in ((words, zero), (pw, words), (words, pw)):
+        inter = np.empty(2 * wa.size, dtype=np.uint32)
+        inter[0::2], inter[1::2] = wa, wb
+        z = L.box_muller(torch.from_numpy(inter.view(np.int32)).cuda()).cpu().numpy()
+        ze, zo = onoise.box_muller(wa.astype(np.uint64), wb.astype(np.uint64))
+        assert np.array_equal(z[0::2].view(np.uint32), ze.view(np.uint32)), \
+            f"{int((z[0::2] != ze).sum())} cos outputs differ"
+        assert np.array_equal(z[1::2].view(np.uint32), zo.view(np.uint32)), \
+            f"{int((z[1::2] != zo).sum())} sin outputs differ"
+
+
 @pytest.mark.parametrize("name,p,x0,g", CASES, ids=IDS)
 def test_rollout_single_step_and_trajectory(L, name, p, x0, g):
     print(f"case {name}", flush=True)
@@ -328,10 +351,10 @@ def test_autotuned_tile_keeps_parity(L, tmp_path):
     from paper_2503_12204_amd import autotune as AT
     p, x0, g = W.unicycle_random(n=8, horizon=40, n_samples=512)
     path = str(tmp_path / "tiles.json")
-    e = AT.tune(p, path=path, reps=2)
+    e = AT.tune(p, x0, g, path=path, reps=2)
     assert 1 <= e["S"] <= 64 and e["Tb"] % 2 == 0 and e["us"] > 0
     try:
-        assert AT.tune(p, path=path) == e          # served from the cache
+        assert AT.tune(p, x0, g, path=path) == e   # served from the cache
         assert AT.install_cache(path) == 1
         rng = np.random.default_rng(3)
         ub = _rand_controls(rng, p, 1, spread=0.5)[0].reshape(-1)
