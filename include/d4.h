@@ -183,9 +183,9 @@ int32_t d4_denoise_iter(d4_ctx* ctx, const d4_problem* p, const float* x0, const
  * 2 for d_u = 2, of 4 for d_u = 3) and the replica lanes R per (sample,
  * robot) (1..8; R > 1 lets R lanes share the draws and pair checks of one
  * lane, for problems with too few lanes to fill the GPU), with
- * R * S * n_robots <= 1024.  S changes the grouping of the reward statistics
- * (results change in the last bits); the time block and R change only speed.
- * The batched form keeps its own rule (R = 1).
+ * S * n_robots <= 256 and R * S * n_robots <= 1024.  A tile changes only
+ * speed: every admissible tile gives the same bits.  The batched form keeps
+ * its own rule (R = 1).
  * ------------------------------------------------------------------------ */
 
 /* Install (or, with samples_per_group = 0, remove) a process-wide tile for

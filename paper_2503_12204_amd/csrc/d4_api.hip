@@ -78,8 +78,7 @@ int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStre
 
 // Weighted update of step i: softmax weights from the reward statistics, the
 // weighted sum of the draws and the rescaled deformation.
-int launch_update(const d4_problem* p, const float* eps, const float* r, const float4* partials, int P,
-                  const float* du_in, float* du_out, float* w_out, int* status, float ms, float sigma,
+int launch_update(const d4_problem* p, const float* eps, const float* r, const float* du_in, float* du_out, float* w_out, int* status, float ms, float sigma,
                   float os, hipStream_t st) {
     const int D = p->n_robots * p->horizon * shape_of(p->dyn).du;
     const int M = p->n_samples;
@@ -87,14 +86,12 @@ int launch_update(const d4_problem* p, const float* eps, const float* r, const f
     UpdateArgs a;
     a.eps = eps;
     a.r = r;
-    a.partials = partials;
     a.du_in = du_in;
     a.du_out = du_out;
     a.w_out = w_out;
     a.status = status;
     a.D = D;
     a.M = M;
-    a.P = P;
     a.inv_lam = 1.0f / p->temperature;
     a.normalize = (p->flags & FLAG_NORMALIZE) ? 1 : 0;
     a.ms = ms;
@@ -126,7 +123,6 @@ struct d4_ctx {
     hipGraph_t graph;
     hipGraphExec_t exec;
     float *eps, *r, *w, *du_a, *du_b, *x0, *goal, *ubase, *traj, *stats;
-    float4* partials;
     int* hits;
     int* status;
     uint32_t* iter;
@@ -138,7 +134,6 @@ void free_ctx_buffers(d4_ctx* c) {
     float* fb[] = {c->eps, c->r, c->w, c->du_a, c->du_b, c->x0, c->goal, c->ubase, c->traj, c->stats};
     for (float* f : fb)
         if (f) (void)hipFree(f);
-    if (c->partials) (void)hipFree(c->partials);
     if (c->hits) (void)hipFree(c->hits);
     if (c->status) (void)hipFree(c->status);
     if (c->iter) (void)hipFree(c->iter);
@@ -172,9 +167,7 @@ int enqueue_iteration(d4_ctx* c, hipStream_t st) {
     a.r = c->r;
     a.hits = c->hits;
     a.robots_hit = nullptr;
-    a.partials = c->partials;
     a.iter_dev = c->iter;
-    const int P = (p->n_samples + tile.S - 1) / tile.S;
     for (int i = p->n_steps; i >= 1; --i) {
         a.du_in = du_cur;
         a.step = (uint32_t)i;
@@ -182,7 +175,7 @@ int enqueue_iteration(d4_ctx* c, hipStream_t st) {
         a.sigma = sc.sigma[i];
         int rc = launch_rollfit<false>(p, a, tile, st);
         if (rc) return rc;
-        rc = launch_update(p, c->eps, c->r, c->partials, P, du_cur, du_nxt, nullptr, c->status, sc.ms[i],
+        rc = launch_update(p, c->eps, c->r, du_cur, du_nxt, nullptr, c->status, sc.ms[i],
                            sc.sigma[i], sc.os[i], st);
         if (rc) return rc;
         float* t = du_cur;
@@ -348,23 +341,8 @@ int32_t d4_score_update(const d4_problem* p, const float* r, const float* eps, c
     if (w_out) NEED(w_out);
     if (p->n_samples > 16384)
         return fail(D4_EUNSUPPORTED, "n_samples %d above the 16384 weights one workgroup stages", p->n_samples);
-    // chunk the rewards as the fused kernel's workgroups do, so that a split
-    // sequence of calls reproduces d4_denoise_iter bit for bit
-    const int S = pick_tile(p).S;
-    const int P = (p->n_samples + S - 1) / S;
-    float4* partials = nullptr;
-    HIP_TRY(hipMallocAsync((void**)&partials, sizeof(float4) * (size_t)P, st));
-    hipLaunchKernelGGL(k_reward_partials, dim3((P + 63) / 64), dim3(64), 0, st, r, p->n_samples, S, partials);
-    hipError_t le = hipGetLastError();
-    if (le != hipSuccess) {
-        (void)hipFreeAsync(partials, st);
-        return fail(D4_EHIP, "launch of k_reward_partials failed: %s", hipGetErrorString(le));
-    }
     const Schedule sc = make_schedule(p);
-    rc = launch_update(p, eps, r, partials, P, du_in, du_out, w_out, nullptr, sc.ms[step], sc.sigma[step],
-                       sc.os[step], st);
-    (void)hipFreeAsync(partials, st);
-    return rc;
+    return launch_update(p, eps, r, du_in, du_out, w_out, nullptr, sc.ms[step], sc.sigma[step], sc.os[step], st);
 }
 
 int32_t d4_ctx_create(const d4_problem* p, d4_ctx** out) {
@@ -390,7 +368,6 @@ int32_t d4_ctx_create(const d4_problem* p, d4_ctx** out) {
         {(void**)&c->goal, 4 * n * s.dp}, {(void**)&c->ubase, 4 * D}, {(void**)&c->traj, 4 * n * (T + 1) * s.dx},
         {(void**)&c->stats, sizeof(d4_stats)}, {(void**)&c->hits, 4 * M}, {(void**)&c->status, 4},
         {(void**)&c->iter, 4},
-        {(void**)&c->partials, sizeof(float4) * (M + 1)},
     };
     for (auto& a : allocs) {
         if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {

@@ -15,7 +15,7 @@ struct d4_batch {
     std::vector<BatchInst> insts;
     std::vector<BatchTile> tiles;
     std::vector<BatchRows> rows;
-    long long tot_x0, tot_goal, tot_u, tot_eps, tot_r, tot_part, tot_traj;
+    long long tot_x0, tot_goal, tot_u, tot_eps, tot_r, tot_traj;
     size_t lds_rollfit;
     // device buffers
     BatchInst* d_insts;
@@ -23,7 +23,6 @@ struct d4_batch {
     BatchRows* d_rows;
     float *x0, *goal, *u, *du_a, *du_b, *eps, *r, *traj, *stats;
     int *hits, *status;
-    float4* partials;
     uint32_t* iter;
     bool captured;
     hipStream_t cap_stream;
@@ -48,7 +47,7 @@ double tile_cost(const d4_problem& p) {
 void free_batch(d4_batch* b) {
     void* ptrs[] = {b->d_insts, b->d_tiles, b->d_rows, b->x0,     b->goal,  b->u,      b->du_a,
                     b->du_b,    b->eps,     b->r,      b->traj,   b->stats, b->hits,   b->status,
-                    b->partials, b->iter};
+                    b->iter};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -74,7 +73,6 @@ int enqueue_batch_iteration(d4_batch* b, hipStream_t st) {
     a.eps = b->eps;
     a.r = b->r;
     a.hits = b->hits;
-    a.partials = b->partials;
     a.iter_dev = b->iter;
     a.M = M;
     a.key0 = (uint32_t)(p0.seed & 0xFFFFFFFFull);
@@ -86,7 +84,6 @@ int enqueue_batch_iteration(d4_batch* b, hipStream_t st) {
     ua.rows = b->d_rows;
     ua.eps = b->eps;
     ua.r = b->r;
-    ua.partials = b->partials;
     ua.status = b->status;
     ua.M = M;
     ua.inv_lam = 1.0f / p0.temperature;
@@ -104,7 +101,10 @@ int enqueue_batch_iteration(d4_batch* b, hipStream_t st) {
         ua.ms = sc.ms[i];
         ua.sigma = sc.sigma[i];
         ua.os = sc.os[i];
-        hipLaunchKernelGGL(k_batch_update, dim3((unsigned)b->rows.size()), dim3(256), (size_t)M * 4, st, ua);
+        if (M % 4 == 0)
+            hipLaunchKernelGGL(k_batch_update<true>, dim3((unsigned)b->rows.size()), dim3(256), (size_t)M * 4, st, ua);
+        else
+            hipLaunchKernelGGL(k_batch_update<false>, dim3((unsigned)b->rows.size()), dim3(256), (size_t)M * 4, st, ua);
         HIP_LAUNCH_CHECK("k_batch_update");
         std::swap(du_cur, du_nxt);
     }
@@ -144,7 +144,7 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
     b->probs.assign(probs, probs + count);
     HIP_TRY(hipGetDevice(&b->device));
     const long long M = probs[0].n_samples;
-    long long ox = 0, og = 0, ou = 0, oe = 0, orr = 0, op = 0, ot = 0;
+    long long ox = 0, og = 0, ou = 0, oe = 0, orr = 0, ot = 0;
     size_t lds = 0;
     std::vector<std::pair<double, BatchTile>> tl;
     for (int j = 0; j < count; ++j) {
@@ -160,13 +160,11 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
         in.Tb = t.Tb;
         in.mode = draws_aligned(&p) ? MODE_FUSED_ALIGNED : MODE_FUSED;
         in.D = p.n_robots * p.horizon * s.du;
-        in.P = (int)((M + t.S - 1) / t.S);
         in.x0 = ox;
         in.goal = og;
         in.u = ou;
         in.eps = oe;
         in.r = orr;
-        in.part = op;
         in.traj = ot;
         in.thr2 = thr2_reward(&p);
         const double s2 = 2.0 * (double)p.robot_radius;
@@ -182,7 +180,7 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
         in.inst_id = p.instance_id;
         b->insts.push_back(in);
         const double cost = tile_cost(p);
-        for (int q = 0; q < in.P; ++q) tl.push_back({cost, BatchTile{j, q * t.S, q}});
+        for (long long m0 = 0; m0 < M; m0 += t.S) tl.push_back({cost, BatchTile{j, (int)m0}});
         for (int e0 = 0; e0 < in.D; e0 += ROWS_PER_TILE)
             b->rows.push_back(BatchRows{j, e0, std::min(in.D, e0 + ROWS_PER_TILE)});
         lds = std::max(lds, rollfit_lds(&p, t));
@@ -191,7 +189,6 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
         ou += in.D;
         oe += (long long)in.D * M;
         orr += M;
-        op += in.P;
         ot += (long long)p.n_robots * (p.horizon + 1) * s.dx;
     }
     if (lds > 160 * 1024) {
@@ -206,7 +203,6 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
     b->tot_u = ou;
     b->tot_eps = oe;
     b->tot_r = orr;
-    b->tot_part = op;
     b->tot_traj = ot;
     b->lds_rollfit = lds;
     if (ou >= (1ll << 31) || oe >= (1ll << 40)) {
@@ -228,7 +224,6 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
         {(void**)&b->eps, 4 * (size_t)oe},
         {(void**)&b->r, 4 * (size_t)orr},
         {(void**)&b->hits, 4 * (size_t)orr},
-        {(void**)&b->partials, sizeof(float4) * (size_t)op},
         {(void**)&b->traj, 4 * (size_t)ot},
         {(void**)&b->stats, sizeof(d4_stats) * (size_t)count},
         {(void**)&b->status, 4 * (size_t)count},

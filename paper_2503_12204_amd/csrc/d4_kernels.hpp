@@ -8,7 +8,6 @@
 //                        trajectories read from memory
 //  k_softmax_update    - batch normalisation, softmax weights (p_0 of Section IV-B),
 //                        S[e] = sum_m w_m eps[e][m] and the one-step update (Eq. mbd-denoising)
-//  k_reward_partials   - per-chunk reward statistics feeding k_softmax_update
 //  k_apply_final       - tau.u <- clip(tau.u + Delta U_0), rollout and stats (Algorithm 2)
 //
 // Lane mapping of k_rollfit: one lane per (sample m, robot k) with the sample
@@ -42,26 +41,6 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// Statistics (count, mean, M2, max) of n <= 64 rewards, one thread, fixed
-// order.  Used by every producer of reward statistics so that they agree bit
-// for bit; a single thread avoids cross-lane reads in partially filled waves.
-__device__ __forceinline__ float4 reward_stats_seq(const float* r, int n) {
-#pragma clang fp contract(off)
-    float s = 0.0f, mx = -INFINITY;
-    for (int i = 0; i < n; ++i) {
-        s += r[i];
-        mx = fmaxf(mx, r[i]);
-    }
-    const float cnt = (float)n;
-    const float mean = n > 0 ? s / cnt : 0.0f;
-    float m2 = 0.0f;
-    for (int i = 0; i < n; ++i) {
-        const float d = r[i] - mean;
-        m2 = __builtin_fmaf(d, d, m2);
-    }
-    return make_float4(cnt, mean, m2, mx);
-}
-
 struct RollFitArgs {
     const float* x0;      // [n][dx]
     const float* goal;    // [n][dp]
@@ -72,7 +51,6 @@ struct RollFitArgs {
     float* r;             // [M]
     int* hits;            // [M]
     int* robots_hit;      // [M] or null
-    float4* partials;     // [gridDim] reward statistics of each workgroup, or null
     const uint32_t* iter_dev;  // iteration index in device memory, or null
     int n, T, M, S, Tb;
     float mean_scale, sigma;
@@ -179,10 +157,9 @@ struct Chunk {
 // MODE_FUSED draws, samples and rolls out; it requires Tb to be a multiple of
 // Chunk::STEPS.  MODE_FROM_X reads trajectories instead.
 // One tile: samples m0 .. m0+S-1 of one problem, lanes tid < n*S (the rest of
-// the workgroup idles through the barriers).  Writes the tile's reward
-// statistics to partials[part] when partials is set.
+// the workgroup idles through the barriers).
 template <int DYN, int MODE>
-__device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int part, float* lds) {
+__device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float* lds) {
     using DY = Dyn<DYN>;
     constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
     using PS = PosSlot<DP>;
@@ -420,16 +397,13 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, int p
         a.r[m] = rv;
         a.hits[m] = hs;
         if (a.robots_hit) a.robots_hit[m] = ss;
-        rg[ms] = rv;
     }
-    __syncthreads();
-    if (a.partials && tid == 0) a.partials[part] = reward_stats_seq(rg, min(S, M - m0));
 }
 
 template <int DYN, int MODE>
 __global__ void __launch_bounds__(256) k_rollfit(const RollFitArgs a) {
     extern __shared__ float lds[];
-    rollfit_tile<DYN, MODE>(a, blockIdx.x * a.S, blockIdx.x, lds);
+    rollfit_tile<DYN, MODE>(a, blockIdx.x * a.S, lds);
 }
 
 // Cooperative variant of the fused kernel for problems with few (sample,
@@ -443,7 +417,7 @@ __global__ void __launch_bounds__(256) k_rollfit(const RollFitArgs a) {
 // Lanes: tid = rep * (n*S) + k * S + ms.  LDS: draws [n][G][4][S] floats with
 // G = Tb*d_u/4 + 1, positions [Tb][2n-1][S] slots, masks [2][Tb][S].
 template <int DYN, int MODE>
-__device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, int m0, int part, float* lds) {
+__device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, int m0, float* lds) {
     using DY = Dyn<DYN>;
     constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
     using PS = PosSlot<DP>;
@@ -573,16 +547,13 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
         a.r[m] = rv;
         a.hits[m] = hs;
         if (a.robots_hit) a.robots_hit[m] = ss;
-        rg[ms] = rv;
     }
-    __syncthreads();
-    if (a.partials && tid == 0) a.partials[part] = reward_stats_seq(rg, min(S, M - m0));
 }
 
 template <int DYN>
 __global__ void __launch_bounds__(1024) k_rollfit_coop(const RollFitArgs a, int R) {
     extern __shared__ float lds[];
-    rollfit_coop_tile<DYN, MODE_FUSED>(a, R, blockIdx.x * a.S, blockIdx.x, lds);
+    rollfit_coop_tile<DYN, MODE_FUSED>(a, R, blockIdx.x * a.S, lds);
 }
 
 // eps[e][m] for e < D, m < M; one lane per (Philox block, sample).
@@ -639,91 +610,89 @@ __global__ void __launch_bounds__(256) k_rollout(const float* x0, const float* u
     }
 }
 
-// Chan's pairwise combination of (count, mean, M2, max) summaries.
-__device__ __forceinline__ float4 chan_combine(float4 a, float4 b) {
-#pragma clang fp contract(off)
-    if (b.x == 0.0f) return a;
-    if (a.x == 0.0f) return b;
-    const float nn = a.x + b.x;
-    const float d = b.y - a.y;
-    const float f = b.x / nn;
-    return make_float4(nn, __builtin_fmaf(d, f, a.y), __builtin_fmaf((d * d) * a.x, f, a.z + b.z), fmaxf(a.w, b.w));
-}
-
-__device__ __forceinline__ float4 wave_combine(float4 v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        float4 u;
-        u.x = __shfl_xor(v.x, o, 64);
-        u.y = __shfl_xor(v.y, o, 64);
-        u.z = __shfl_xor(v.z, o, 64);
-        u.w = __shfl_xor(v.w, o, 64);
-        // combine in a fixed order (lower lane first) so every lane agrees bit for bit
-        v = ((threadIdx.x & o) == 0) ? chan_combine(v, u) : chan_combine(u, v);
-    }
-    return v;
-}
-
-// Reward statistics of consecutive S-sample chunks (S <= 64), computed exactly
-// as the fused kernel's tail computes them for its workgroups of S samples.
-static __global__ void k_reward_partials(const float* r, int M, int S, float4* partials) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m0 = b * S;
-    if (m0 < M) partials[b] = reward_stats_seq(r + m0, min(S, M - m0));
-}
-
 struct UpdateArgs {
     const float* eps;        // [D][M]
     const float* r;          // [M]
-    const float4* partials;  // [P] reward statistics
     const float* du_in;      // [D]
     float* du_out;           // [D]
     float* w_out;            // [M] or null (written by workgroup 0)
     int* status;             // set to D4_ENONFINITE on a non-finite reward, or null
-    int D, M, P;
+    int D, M;
     float inv_lam;
     int normalize;
     float ms, sigma, os;
 };
 
+// Sum and maximum over the workgroup (256 lanes at most), the same bits in
+// every lane and every workgroup of the same size.
+__device__ __forceinline__ void block_sum_max(float& s, float& mx, float* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    s = wave_sum(s);
+    mx = wave_max(mx);
+    __syncthreads();
+    if (lane == 0) {
+        red[wave] = s;
+        red[8 + wave] = mx;
+    }
+    __syncthreads();
+    s = red[0];
+    mx = red[8];
+    for (int w = 1; w < nw; ++w) {
+        s += red[w];
+        mx = fmaxf(mx, red[8 + w]);
+    }
+}
+
 // Softmax weights (Section IV-B, p_0 proportional to exp(r/lambda) of the
 // batch-normalised rewards) and the one-step update (Eq. mbd-denoising):
-// every workgroup combines the reward statistics, stages the unnormalised
-// weights exp(z_m - z_max) in LDS with their sum, then reduces rows of eps,
-// one wave per row, and applies the normaliser once per row.
+// every workgroup stages the rewards in LDS, takes their mean, population
+// variance and maximum in a fixed order (two passes), replaces them by the
+// unnormalised weights exp(z_m - z_max) with their sum, then reduces rows of
+// eps, one wave per row, and applies the normaliser once per row.  All
+// workgroups of one launch (and of the batched form, which uses the same
+// 256-lane workgroups) compute the same weights bit for bit.
 template <bool VEC>
 __device__ __forceinline__ void softmax_update_rows(const UpdateArgs& a, int e_begin, int e_step, int e_end,
                                                     bool first, float* wl) {
-    __shared__ float4 red4[4];
-    __shared__ float reds[4];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+#pragma clang fp contract(off)
+    __shared__ float red[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, bd = blockDim.x;
     const int M = a.M;
-    float4 st = make_float4(0.0f, 0.0f, 0.0f, -INFINITY);
-    for (int i = tid; i < a.P; i += blockDim.x) st = chan_combine(st, a.partials[i]);
-    st = wave_combine(st);
-    if (lane == 0) red4[wave] = st;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    if (VEC) {
+        const f4* r4 = reinterpret_cast<const f4*>(a.r);
+        for (int i = tid; i < (M >> 2); i += bd) reinterpret_cast<f4*>(wl)[i] = r4[i];
+    } else {
+        for (int i = tid; i < M; i += bd) wl[i] = a.r[i];
+    }
     __syncthreads();
-    st = red4[0];
-    for (int w = 1; w < nw; ++w) st = chan_combine(st, red4[w]);
-    const bool bad = !isfinite(st.y) || !isfinite(st.z) || !isfinite(st.w);
+    float sum = 0.0f, mx = -INFINITY;
+    for (int i = tid; i < M; i += bd) {
+        sum += wl[i];
+        mx = fmaxf(mx, wl[i]);
+    }
+    block_sum_max(sum, mx, red);
+    const float mean = sum / (float)M;
+    float q = 0.0f, unused = -INFINITY;
+    for (int i = tid; i < M; i += bd) {
+        const float d = wl[i] - mean;
+        q = __builtin_fmaf(d, d, q);
+    }
+    block_sum_max(q, unused, red);
+    const bool bad = !isfinite(mean) || !isfinite(q) || !isfinite(mx);
     float mu = 0.0f, scale = a.inv_lam;
     if (a.normalize) {
-        mu = st.y;
-        scale = a.inv_lam / fmaxf(sqrtf(st.z / st.x), 1e-6f);
+        mu = mean;
+        scale = a.inv_lam / fmaxf(sqrtf(q / (float)M), 1e-6f);
     }
-    const float zmax = (st.w - mu) * scale;
+    const float zmax = (mx - mu) * scale;
     float se = 0.0f;
-    for (int i = tid; i < M; i += blockDim.x) {
-        const float e = bad ? 1.0f : __expf((a.r[i] - mu) * scale - zmax);
+    for (int i = tid; i < M; i += bd) {
+        const float e = bad ? 1.0f : __expf(__builtin_fmaf(wl[i] - mu, scale, -zmax));
         wl[i] = e;
         se += e;
     }
-    se = wave_sum(se);
-    __syncthreads();
-    if (lane == 0) reds[wave] = se;
-    __syncthreads();
-    se = reds[0];
-    for (int w = 1; w < nw; ++w) se += reds[w];
+    block_sum_max(se, unused, red);
     const float inv_se = 1.0f / se;
     if (first) {
         if (a.w_out)
@@ -735,18 +704,22 @@ __device__ __forceinline__ void softmax_update_rows(const UpdateArgs& a, int e_b
         const float* row = a.eps + (size_t)e * M;
         float acc = 0.0f;
         if (VEC) {
-            typedef float f4 __attribute__((ext_vector_type(4)));
             const f4* r4 = reinterpret_cast<const f4*>(row);
             const f4* w4 = reinterpret_cast<const f4*>(wl);
             const int M4 = M >> 2;
+            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
 #pragma unroll 8
             for (int i = lane; i < M4; i += 64) {
                 const f4 x = __builtin_nontemporal_load(r4 + i);
                 const f4 b = w4[i];
-                acc += x.x * b.x + x.y * b.y + x.z * b.z + x.w * b.w;
+                c0 = __builtin_fmaf(x.x, b.x, c0);
+                c1 = __builtin_fmaf(x.y, b.y, c1);
+                c2 = __builtin_fmaf(x.z, b.z, c2);
+                c3 = __builtin_fmaf(x.w, b.w, c3);
             }
+            acc = (c0 + c1) + (c2 + c3);
         } else {
-            for (int i = lane; i < M; i += 64) acc += row[i] * wl[i];
+            for (int i = lane; i < M; i += 64) acc = __builtin_fmaf(row[i], wl[i], acc);
         }
         acc = wave_sum(acc);
         if (lane == 0) a.du_out[e] = a.os * (a.du_in[e] * a.ms + s_inv * acc);
@@ -887,15 +860,15 @@ __global__ void __launch_bounds__(256) k_apply_final(const FinalArgs a) {
 // team size, horizon, dynamics and limits are its own.  Offsets count floats
 // (or samples) into packed arrays in instance order.
 struct BatchInst {
-    int n, T, dyn, S, Tb, mode, D, P;
-    long long x0, goal, u, eps, r, part, traj;
+    int n, T, dyn, S, Tb, mode, D;
+    long long x0, goal, u, eps, r, traj;
     float thr2, safe2, w_safe, d0_floor, goal_tol;
     float ulo[3], uhi[3];
     StepConsts sc;
     uint32_t inst_id;
 };
 struct BatchTile {   // samples m0 .. m0+S-1 of one instance
-    int inst, m0, part;
+    int inst, m0;
 };
 struct BatchRows {   // rows e0 .. e1-1 of one instance's update
     int inst, e0, e1;
@@ -911,7 +884,6 @@ struct BatchStepArgs {
     float* eps;
     float* r;
     int* hits;
-    float4* partials;
     const uint32_t* iter_dev;
     int M;
     uint32_t key0, key1, step, flags;
@@ -933,7 +905,6 @@ static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArg
     a.r = b.r + in.r;
     a.hits = b.hits + in.r;
     a.robots_hit = nullptr;
-    a.partials = b.partials + in.part;
     a.iter_dev = b.iter_dev;
     a.n = in.n;
     a.T = in.T;
@@ -959,16 +930,16 @@ static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArg
     const bool al = in.mode == MODE_FUSED_ALIGNED;
     switch (in.dyn) {
         case HOLO2D:
-            if (al) rollfit_tile<HOLO2D, MODE_FUSED_ALIGNED>(a, tl.m0, tl.part, lds);
-            else rollfit_tile<HOLO2D, MODE_FUSED>(a, tl.m0, tl.part, lds);
+            if (al) rollfit_tile<HOLO2D, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
+            else rollfit_tile<HOLO2D, MODE_FUSED>(a, tl.m0, lds);
             break;
         case HOLO3D:
-            if (al) rollfit_tile<HOLO3D, MODE_FUSED_ALIGNED>(a, tl.m0, tl.part, lds);
-            else rollfit_tile<HOLO3D, MODE_FUSED>(a, tl.m0, tl.part, lds);
+            if (al) rollfit_tile<HOLO3D, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
+            else rollfit_tile<HOLO3D, MODE_FUSED>(a, tl.m0, lds);
             break;
         default:
-            if (al) rollfit_tile<UNICYCLE, MODE_FUSED_ALIGNED>(a, tl.m0, tl.part, lds);
-            else rollfit_tile<UNICYCLE, MODE_FUSED>(a, tl.m0, tl.part, lds);
+            if (al) rollfit_tile<UNICYCLE, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
+            else rollfit_tile<UNICYCLE, MODE_FUSED>(a, tl.m0, lds);
             break;
     }
 }
@@ -978,7 +949,6 @@ struct BatchUpdArgs {
     const BatchRows* rows;
     const float* eps;
     const float* r;
-    const float4* partials;
     const float* du_in;
     float* du_out;
     int* status;  // [count]
@@ -988,28 +958,28 @@ struct BatchUpdArgs {
     float ms, sigma, os;
 };
 
-// Softmax weights and the update of one row range per workgroup.
-static __global__ void __launch_bounds__(256) k_batch_update(const BatchUpdArgs b) {
+// Softmax weights and the update of one row range per workgroup (VEC: the
+// sample count is a multiple of 4, so rows are 16-byte aligned).
+template <bool VEC>
+__global__ void __launch_bounds__(256) k_batch_update(const BatchUpdArgs b) {
     extern __shared__ float wl[];
     const BatchRows rt = b.rows[blockIdx.x];
     const BatchInst& in = b.insts[rt.inst];
     UpdateArgs a;
     a.eps = b.eps + in.eps;
     a.r = b.r + in.r;
-    a.partials = b.partials + in.part;
     a.du_in = b.du_in + in.u;
     a.du_out = b.du_out + in.u;
     a.w_out = nullptr;
     a.status = b.status + rt.inst;
     a.D = in.D;
     a.M = b.M;
-    a.P = in.P;
     a.inv_lam = b.inv_lam;
     a.normalize = b.normalize;
     a.ms = b.ms;
     a.sigma = b.sigma;
     a.os = b.os;
-    softmax_update_rows<true>(a, rt.e0, blockDim.x >> 6, rt.e1, rt.e0 == 0, wl);
+    softmax_update_rows<VEC>(a, rt.e0, blockDim.x >> 6, rt.e1, rt.e0 == 0, wl);
 }
 
 struct BatchFinalArgs {

@@ -401,9 +401,9 @@ def test_cooperative_kernel_is_bit_identical(L, dyn, n, T, M, S, Tb):
 
 def test_negative_rewards_in_partial_waves(L):
     """A packed 3-robot team (collision penalties make rewards negative) with
-    workgroups smaller than a wave: the reward statistics of the fused kernel
-    and of the standalone update agree, so the split calls reproduce the graph
-    iteration bit for bit."""
+    workgroups smaller than a wave: the split calls reproduce the graph
+    iteration bit for bit (the batch statistics include the maximum of
+    all-negative rewards)."""
     rng = np.random.default_rng(21)
     p, x0, g = W.random_instance(rng, W.HOLO2D, 3, 30, 70, box=1.6, min_sep=0.5)
     p = p.replace(n_steps=8, w_safe=3.0)
@@ -419,3 +419,33 @@ def test_negative_rewards_in_partial_waves(L):
     ctx.denoise_iter(_cu(x0), _cu(g), u, 0)
     ctx.close()
     assert np.array_equal(_np(u), expect)
+
+
+@pytest.mark.parametrize("dyn,n,T,M", [(W.HOLO3D, 7, 23, 301), (W.UNICYCLE, 12, 40, 256), (W.HOLO2D, 2, 9, 64)])
+def test_tile_does_not_change_results(L, dyn, n, T, M):
+    """Samples per workgroup, time block and replica lanes change speed only:
+    a whole iteration gives the same bits for every admissible tile."""
+    from paper_2503_12204_amd import autotune as AT
+    rng = np.random.default_rng(n + T)
+    p, x0, g = W.random_instance(rng, dyn, n, T, M, box=max(3.0, n ** 0.5 * 1.5), min_sep=0.6)
+    p = p.replace(n_steps=5)
+    u0 = _rand_controls(rng, p, 1, spread=0.5)[0]
+    cs = 4 if p.du == 3 else 2
+    tiles = [(1, cs, 1), (3, 2 * cs, 1), (min(64, 256 // n), 4 * cs, 1), (2, 4 * cs, 2), (4, cs, 4)]
+    plans = []
+    for S, Tb, R in tiles:
+        if S * n > 256 or R * S * n > 1024:
+            continue
+        AT.set_tile(p.dyn, p.n_robots, p.horizon, S, Tb, R)
+        try:
+            ctx = L.Context(p)
+            u = _cu(u0)
+            st = ctx.denoise_iter(_cu(x0), _cu(g), u, 0)
+            ctx.close()
+        finally:
+            AT.clear_tile(p.dyn, p.n_robots, p.horizon)
+        plans.append((S, Tb, R, _np(u), st["reward"]))
+    assert len(plans) >= 3
+    for S, Tb, R, u, rew in plans[1:]:
+        assert np.array_equal(u, plans[0][3]), f"tile {(S, Tb, R)}"
+        assert rew == plans[0][4]
