@@ -15,25 +15,37 @@ the same numbers:
 * Box-Muller (Box and Muller, 1958) on word pairs (x0, x1) and (x2, x3):
   rho = sqrt(-2 ln u_a), z_even = rho cos(2 pi u_b), z_odd = rho sin(2 pi u_b).
 * ln and the sine/cosine are evaluated in IEEE FP32, one correctly rounded
-  operation at a time, no fused multiply-add, in the order written below:
-  - ln: u = 2^e f with f in [0.75, 1.5); s = (f - 1) / (f + 1);
-    ln f = 2 (s + s (s^2 q(s^2))), q the atanh series 1/3 + s^2/5 + s^4/7 + s^6/9
-    in Horner form; ln u = e * LN2_HI + (ln f + e * LN2_LO), LN2_HI = 355/512,
+  operation at a time, in the order written below; fma(a, b, c) is a*b + c
+  rounded once (IEEE fusedMultiplyAdd), everything else is a single operation:
+  - ln: u = 2^e f with f in [0.75, 1.5); s = (f - 1) / (f + 1); s2 = s*s;
+    q = fma(fma(fma(1/9, s2, 1/7), s2, 1/5), s2, 1/3) (the atanh series
+    1/3 + s^2/5 + s^4/7 + s^6/9 in Horner form); t = fma(s*s2, q, s);
+    ln u = fma(e, LN2_HI, fma(e, LN2_LO, 2 t)), LN2_HI = 355/512,
     LN2_LO = RN32(ln 2 - 355/512).
   - angle: u_b = (2 j + 1) 2^-24 with j = x_b >> 9; quadrant
     q = (2 j + 1 + 2^21) >> 22 in 0..4, r = ((2 j + 1) - q 2^22) 2^-23 in
-    [-1/4, 1/4] (both exact), y = r * RN32(pi);
-    sin y = y + y (y^2 P(y^2)), P the Taylor series -1/3! + y^2/5! - y^4/7! + y^6/9!;
-    cos y = 1 + y^2 C(y^2), C = -1/2! + y^2/4! - y^4/6! + y^6/8!;
+    [-1/4, 1/4] (both exact), y = r * RN32(pi), y2 = y*y;
+    sin y = fma(y*y2, P, y), P = fma(fma(1/9!, y2, -1/7!), y2, 1/5!) * ... in
+    Horner form: P = fma(fma(fma(1/9!, y2, -1/7!), y2, 1/5!), y2, -1/3!);
+    cos y = fma(y2, C, 1), C = fma(fma(fma(1/8!, y2, -1/6!), y2, 1/4!), y2, -1/2!);
     then rotate by q quarter turns.
   Series coefficients are the FP32 roundings of the exact rationals.  The
   series lengths are the shortest that keep ln, sin and cos within 2 ulp (or
   2^-23 absolute near zeros of sin and cos) over every reachable input.
 
+fma32 obtains the single rounding from FP64: the product of two FP32
+numbers is exact in FP64, the sum with c is rounded to odd in FP64 (round to
+nearest, then the exact TwoSum error decides whether to step to the odd
+neighbour), and rounding that to FP32 is the correctly rounded fused result
+because FP64 carries more than 24 + 2 bits (Boldo and Melquiond, "Emulation
+of FMA and correctly rounded sums: proved algorithms using rounding to odd",
+IEEE Trans. Computers 57(4), 2008).
+
 Pinned by the published Philox4x32-10 known-answer vectors
 (tests/golden/philox4x32_10_kat.txt), by exhaustive error bounds of ln and
-sin/cos against FP64 over every reachable input, and by moment and
-Kolmogorov-Smirnov tests of the normals (tests/test_oracle_noise.py).
+sin/cos against FP64 over every reachable input, by exact rational checks of
+fma32, and by moment and Kolmogorov-Smirnov tests of the normals
+(tests/test_oracle_noise.py).
 """
 import numpy as np
 
@@ -69,6 +81,21 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
     return c0, c1, c2, c3
 
 
+def fma32(a, b, c):
+    """a*b + c rounded once to FP32 (correctly rounded fused multiply-add)."""
+    a = np.asarray(a, dtype=F).astype(np.float64)
+    b = np.asarray(b, dtype=F).astype(np.float64)
+    c = np.asarray(c, dtype=F).astype(np.float64)
+    p = a * b                                   # exact: 24 + 24 bits fit in 53
+    s = p + c                                   # nearest FP64
+    bv = s - p                                  # TwoSum: s + err == p + c exactly
+    err = (p - (s - bv)) + (c - bv)
+    even = (s.view(np.uint64) & np.uint64(1)) == 0
+    step = (err != 0) & even                    # inexact and even: take the odd neighbour
+    s = np.where(step, np.nextafter(s, np.where(err > 0, np.inf, -np.inf)), s)
+    return s.astype(F)
+
+
 def uniform24(x):
     """(2 (x >> 9) + 1) * 2^-24 as FP32 (exact)."""
     j = (np.asarray(x, dtype=np.uint64) >> np.uint64(9)).astype(np.int64)
@@ -90,17 +117,13 @@ def ln32(u):
     big = f >= F(1.5)
     f = np.where(big, f * F(0.5), f).astype(F)
     e = np.where(big, e + 1, e)
-    s = (f - F(1)) / (f + F(1))
+    s = ((f - F(1)) / (f + F(1))).astype(F)
     s2 = s * s
-    q = _A9
-    q = q * s2 + _A7
-    q = q * s2 + _A5
-    q = q * s2 + _A3
-    q = q.astype(F) if isinstance(q, np.ndarray) else F(q)
-    t = s + s * (s2 * q)
+    q = fma32(fma32(fma32(_A9, s2, _A7), s2, _A5), s2, _A3)
+    t = fma32(s * s2, q, s)
     lnf = F(2) * t
     ef = e.astype(F)
-    return (ef * _LN2_HI + (lnf + ef * _LN2_LO)).astype(F)
+    return fma32(ef, _LN2_HI, fma32(ef, _LN2_LO, lnf))
 
 
 # --- FP32 sine and cosine of 2 pi u_b
@@ -118,14 +141,10 @@ def sincos2pi32(x):
     r = rn.astype(F) * F(2.0 ** -23)
     y = r * _PI
     y2 = y * y
-    sp = _S9 * y2 + _S7
-    sp = sp * y2 + _S5
-    sp = sp * y2 + _S3
-    sn = y + y * (y2 * sp)
-    cp = _C8 * y2 + _C6
-    cp = cp * y2 + _C4
-    cp = cp * y2 + _C2
-    cs = F(1) + y2 * cp
+    sp = fma32(fma32(fma32(_S9, y2, _S7), y2, _S5), y2, _S3)
+    sn = fma32(y * y2, sp, y)
+    cp = fma32(fma32(fma32(_C8, y2, _C6), y2, _C4), y2, _C2)
+    cs = fma32(y2, cp, F(1))
     q = q & 3
     sin_o = np.select([q == 0, q == 1, q == 2], [sn, cs, -sn], -cs).astype(F)
     cos_o = np.select([q == 0, q == 1, q == 2], [cs, -sn, -cs], sn).astype(F)

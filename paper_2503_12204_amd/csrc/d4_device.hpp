@@ -3,8 +3,9 @@
 //  - Counter-based normal draws for the sampling step of Algorithm 1
 //    (Eq. mc): Philox4x32-10 (Salmon et al., SC'11) feeding a Box-Muller
 //    transform whose ln and sin/cos are evaluated in FP32 one correctly
-//    rounded operation at a time (no contraction), so the draws are the
-//    same bits on every implementation of the recipe.
+//    rounded operation (or fused multiply-add) at a time, in a fixed order
+//    with no other contraction, so the draws are the same bits on every
+//    implementation of the recipe.
 //  - RK4 steps of the three robot models (Section III feasibility condition,
 //    Section V models).  The double integrator's RK4 step is evaluated in
 //    its exact closed form p + v dt + a dt^2/2, v + a dt (RK4 is exact when
@@ -77,7 +78,8 @@ __device__ __forceinline__ float sqrt_rn_normal(float x) {
 
 // Natural log of a uniform in (0, 1): u = 2^e f, f in [0.75, 1.5),
 // ln f = 2 atanh(s), s = (f - 1)/(f + 1), atanh by its Taylor series in
-// Horner form through s^9, e*ln2 split as 355/512 plus the FP32 remainder.
+// fused Horner form through s^9, e*ln2 split as 355/512 (exact products
+// with e) plus the FP32 remainder.
 // Within 2 ulp of ln u for every uniform the recipe produces.
 __device__ __forceinline__ float ln_unit(float u) {
 #pragma clang fp contract(off)
@@ -92,15 +94,10 @@ __device__ __forceinline__ float ln_unit(float u) {
     e += big ? 1 : 0;
     const float s = div_rn_moderate(f - 1.0f, f + 1.0f);
     const float s2 = s * s;
-    float q = A9 * s2 + A7;
-    q = q * s2 + A5;
-    q = q * s2 + A3;
-    const float t = s + s * (s2 * q);
-    const float lnf = 2.0f * t;
+    const float q = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(A9, s2, A7), s2, A5), s2, A3);
+    const float t = __builtin_fmaf(s * s2, q, s);
     const float ef = (float)e;
-    const float hi = ef * LN2_HI;
-    const float lo = ef * LN2_LO;
-    return hi + (lnf + lo);
+    return __builtin_fmaf(ef, LN2_HI, __builtin_fmaf(ef, LN2_LO, 2.0f * t));
 }
 
 // sin and cos of 2 pi u_b for u_b = (2j + 1) 2^-24, j = word >> 9: exact
@@ -117,14 +114,10 @@ __device__ __forceinline__ void sincos_2pi_word(uint32_t word, float& sn_o, floa
     const float r = (float)rn * 0x1.0p-23f;
     const float y = r * PI_F;
     const float y2 = y * y;
-    float sp = S9 * y2 + S7;
-    sp = sp * y2 + S5;
-    sp = sp * y2 + S3;
-    const float sn = y + y * (y2 * sp);
-    float cp = C8 * y2 + C6;
-    cp = cp * y2 + C4;
-    cp = cp * y2 + C2;
-    const float cs = 1.0f + y2 * cp;
+    const float sp = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(S9, y2, S7), y2, S5), y2, S3);
+    const float sn = __builtin_fmaf(y * y2, sp, y);
+    const float cp = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(C8, y2, C6), y2, C4), y2, C2);
+    const float cs = __builtin_fmaf(y2, cp, 1.0f);
     // rotate by q quarter turns: swap on odd q, then exact sign flips
     // (sin: q = 2, 3; cos: q = 1, 2)
     const uint32_t qq = (uint32_t)q & 3u;

@@ -112,3 +112,47 @@ def test_sample_subset_matches_full_draw():
     full = noise.draw(5, 1, 0, 3, 40, 13)
     sub = noise.draw(5, 1, 0, 3, 40, 13, samples=[0, 7, 39, 12])
     assert np.array_equal(sub, full[:, [0, 7, 39, 12]])
+
+
+def _round_to_f32_exact(x):
+    """Nearest FP32 (ties to even) of an exact rational, by bisection on neighbours."""
+    from fractions import Fraction
+    g = np.float32(float(x))                    # within one FP32 step of x
+    best = None
+    for cand in (np.nextafter(g, np.float32(-np.inf)), g, np.nextafter(g, np.float32(np.inf))):
+        d = abs(Fraction(float(cand)) - x)
+        if best is None or d < best[0] or (d == best[0] and (int(cand.view(np.uint32)) & 1) == 0):
+            best = (d, cand)
+    return best[1]
+
+
+def test_fma32_is_correctly_rounded():
+    """fma32 against exact rational arithmetic: random operands, near-total
+    cancellation (the hard cases for a double rounding), exact midpoints and
+    the operand ranges of the ln and sin/cos recipes."""
+    from fractions import Fraction
+    rng = np.random.default_rng(7)
+    cases = []
+    for _ in range(3000):
+        a, b = np.float32(rng.normal() * 4), np.float32(rng.normal())
+        cases.append((a, b, np.float32(rng.normal())))
+        # c close to -a*b: the exact sum keeps bits far below FP32's last place
+        cases.append((a, b, np.float32(-(np.float64(a) * np.float64(b)) * (1 + rng.normal() * 1e-6))))
+        # c in [1, 2) and a*b half an FP32 step of c (an exact midpoint, ties
+        # to even), or a hair above or below it
+        m = np.float32(rng.uniform(1, 2))
+        sgn = rng.choice([-1.0, 1.0])
+        for b in (1.0, 1.0 + 2.0 ** -20, 1.0 - 2.0 ** -20):
+            cases.append((np.float32(2.0 ** -24), np.float32(sgn * b), m))
+        # a*b = 2^-24 - 2^-70: the exact sum sits just inside an FP32 midpoint
+        # but rounds onto it in FP64, where a plain double rounding goes wrong
+        # whenever c's last bit is odd
+        for cm in (m, np.nextafter(m, np.float32(2))):
+            cases.append((np.float32(2.0 ** -24 * (1 + 2.0 ** -23)), np.float32(sgn * (1 - 2.0 ** -23)), cm))
+    for s2 in np.float32(rng.uniform(0, 0.05, 500)):
+        cases.append((np.float32(1) / np.float32(9), s2, np.float32(1) / np.float32(7)))
+    a, b, c = (np.array(v, dtype=np.float32) for v in zip(*cases))
+    got = noise.fma32(a, b, c)
+    for ai, bi, ci, gi in zip(a, b, c, got):
+        exact = Fraction(float(ai)) * Fraction(float(bi)) + Fraction(float(ci))
+        assert gi.view(np.uint32) == _round_to_f32_exact(exact).view(np.uint32), (ai, bi, ci)
