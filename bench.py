@@ -31,23 +31,35 @@ if ROOT not in sys.path:
 VALU_PEAK = 256 * 4 * 16 * 2.4e9      # lane-operations per second
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic VALU operations per robot*step*sample of the fused kernel.
-# Per standard normal: Philox4x32-10 is 10 rounds of two 32x32->64 products
-# (4 ops), four XORs and two key additions = 100 ops per 4 normals (25 each);
-# Box-Muller per pair: uniform (4), ln (30), sqrt and scale (2), sin/cos with
-# quadrant rotation (36), two products (2) = 74 per pair, 37 per normal;
-# 62 ops per normal in all.  Per control component: base + mean, sample, clamp
-# = 4.  Dynamics per step: double integrator 5 per axis; unicycle 13 (two
-# heading updates, two sin/cos pairs, Simpson sums).  Goal term 2 d_p + 3.
-# Pair check 2 d_p + 3 per pair, (n - 1)/2 pairs per robot-step.  Mask 4.
-OPS_PER_NORMAL = 62
+# Algorithmic VALU operations per robot*step*sample of the fused kernel: the
+# operations each step of the method needs in its leanest gfx950 form (one
+# VALU instruction per arithmetic step, a fused multiply-add or a 32x32->64
+# product counted once), independent of how the kernel schedules them.
+#  - standard normal: Philox4x32-10 = 10 rounds of two 32x32->64 products and
+#    the XORs with the other words and the round key, plus the counter set-up:
+#    50 per block of 4 normals (12.5);
+#    Box-Muller per pair: uniform 3, ln 25 (division 8), -2 ln and the
+#    corrected square root 7, sin/cos with the quadrant rotation 27, two
+#    products 2 = 64 per pair (32); 44.5 per normal in all
+#  - sampled control: fma, fma, max, min = 4 per component
+#  - dynamics per step: double integrator 5 per axis; unicycle 13 (two heading
+#    updates, two hardware sin/cos pairs, Simpson sums)
+#  - goal term: 2 d_p + 3 (squared distance, square root, fused step, sum)
+#  - bounding box of the block: 2 d_p
+#  - broad phase: (n - 1)/2 partners per robot and block of Tb steps, 4 d_p + 2
+#    each (two differences and a max per axis, squares and sums, compare, or)
+#  - collision flags: 3
+# The exact pair checks of partners the broad phase keeps are data dependent
+# and not counted (under 1% of pairs on the benchmark workloads).
+OPS_PER_NORMAL = 44.5
 
 
-def ops_per_unit(dyn, n):
+def ops_per_unit(dyn, n, steps_per_block):
     from paper_2503_12204_amd import workloads as W
     dx, du, dp = W.dims(dyn)
     dyn_ops = 13 if dyn == W.UNICYCLE else 5 * dp
-    return du * OPS_PER_NORMAL + 4 * du + dyn_ops + (2 * dp + 3) + (n - 1) / 2.0 * (2 * dp + 3) + 4
+    broad = (n - 1) / 2.0 * (4 * dp + 2) / steps_per_block
+    return du * OPS_PER_NORMAL + 4 * du + dyn_ops + (2 * dp + 3) + 2 * dp + broad + 3
 
 
 WORKLOADS = {
@@ -129,8 +141,9 @@ def stored_traffic(workload):
 
 
 def time_fused_kernel(L, p, x0, g, reps=30):
-    """Average duration of the fused sample+rollout+reward kernel, bracketed by
-    HIP events on the stream it is launched on (torch's current stream)."""
+    """Average duration of the fused sample+rollout+reward kernel on the zero
+    plan, bracketed by HIP events on the stream it is launched on (torch's
+    current stream).  Used for the counter runs."""
     import torch
     D, M = p.D, p.n_samples
     eps = torch.empty((D, M), dtype=torch.float32, device="cuda")
@@ -139,15 +152,43 @@ def time_fused_kernel(L, p, x0, g, reps=30):
     ub = torch.zeros(D, dtype=torch.float32, device="cuda")
     du = torch.zeros(D, dtype=torch.float32, device="cuda")
     for _ in range(3):
-        L.sample_rollout_fitness(p, x0, g, ub, du, 0, 100, eps, r, hits)
+        L.sample_rollout_fitness(p, x0, g, ub, du, 0, p.n_steps, eps, r, hits)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for k in range(reps):
-        L.sample_rollout_fitness(p, x0, g, ub, du, 0, 100 - (k % 100), eps, r, hits)
+        L.sample_rollout_fitness(p, x0, g, ub, du, 0, p.n_steps - (k % p.n_steps), eps, r, hits)
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def time_fused_kernel_in_iteration(L, p, x0, g, u, iteration):
+    """Average duration of the fused kernel over the N denoising steps of one
+    iteration from plan u.  The iteration runs first through the split calls
+    (the launches of d4_denoise_iter), keeping each step's Delta U_i; the N
+    fused launches are then replayed back to back on those inputs between
+    two HIP events on the launch stream."""
+    import torch
+    D, M = p.D, p.n_samples
+    eps = torch.empty((D, M), dtype=torch.float32, device="cuda")
+    r = torch.empty(M, dtype=torch.float32, device="cuda")
+    hits = torch.empty(M, dtype=torch.int32, device="cuda")
+    ub = u.reshape(-1).contiguous()
+    w = torch.empty(M, dtype=torch.float32, device="cuda")
+    dus = [torch.zeros(D, dtype=torch.float32, device="cuda")]
+    steps = list(range(p.n_steps, 0, -1))
+    for i in steps:
+        L.sample_rollout_fitness(p, x0, g, ub, dus[-1], iteration, i, eps, r, hits)
+        dus.append(L.score_update(p, r, eps, dus[-1], i, None, w)[0])
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for k, i in enumerate(steps):
+        L.sample_rollout_fitness(p, x0, g, ub, dus[k], iteration, i, eps, r, hits)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / len(steps) * 1e-3
 
 
 def main():
@@ -235,13 +276,17 @@ def main():
     units = p.n_robots * p.horizon * p.n_samples * p.n_steps
     value = units / (elapsed / args.steps)
 
-    t_k = time_fused_kernel(L, p, x0, g)
-    ops = ops_per_unit(p.dyn, p.n_robots) * p.n_robots * p.horizon * p.n_samples
+    t_k = time_fused_kernel_in_iteration(L, p, x0, g, u, args.warmup + args.steps + 1)
+    from paper_2503_12204_amd import autotune as AT
+    S_t, Tb_t, R_t = AT.get_tile(p)
+    opu = ops_per_unit(p.dyn, p.n_robots, Tb_t)
+    ops = opu * p.n_robots * p.horizon * p.n_samples
     achieved = ops / t_k
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                 "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK, "traffic": stored_traffic(args.workload),
                 "kernel": "k_rollfit (fused sample+rollout+reward)", "kernel_us": t_k * 1e6,
-                "ops_per_unit": ops_per_unit(p.dyn, p.n_robots)}
+                "ops_per_unit": opu, "tile": {"samples_per_group": S_t, "steps_per_block": Tb_t,
+                                              "replicas": R_t}}
     out = {
         "metric": "robot*step*samples/s in rollout+fitness (whole denoising iteration)",
         "value": value, "unit": "robot*step*samples/s", "n_gpus": 1, "steps": args.steps,
