@@ -296,7 +296,8 @@ def main():
                    "robots": p.n_robots, "horizon": p.horizon, "samples": p.n_samples,
                    "denoising_steps": p.n_steps, "dynamics": W.DYN_NAMES[p.dyn]},
         "roofline": roofline,
-        "last_iteration": {"reward": st["reward"], "hits": st["hits"], "success": st["success"]},
+        "last_iteration": {"reward": st["reward"], "hits": st["hits"], "success": st["success"],
+                           "at_goal": st["at_goal"]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

@@ -84,7 +84,10 @@ typedef struct d4_stats {
     float objective;        /* Eq. objective: fraction of robot-steps at the goal */
     int32_t hits;           /* colliding pairs (reward threshold) summed over t */
     int32_t robots_hit;     /* robot-steps with r_safe != 0 */
-    int32_t success;        /* safety (> 2 R_a) at every step and terminal condition */
+    int32_t success;        /* conflict-free: every pair farther apart than 2 R_a at t = 1..T
+                               (feasibility holds by construction; Sec. V-A reads success as
+                               feasible and conflict-free) */
+    int32_t at_goal;        /* terminal condition: every robot within goal_tol of its goal at t = T */
     int32_t status;         /* D4_OK or D4_ENONFINITE */
 } d4_stats;
 

@@ -16,8 +16,10 @@ Readings (the paper is ambiguous or silent):
   FP32 as ((dx*dx + dy*dy) + dz*dz), each operation rounded, and thr2 is the
   FP32 rounding of the FP64 square; on FP64 positions everything is FP64.
 * success: every pair strictly farther apart than 2 R_a at t = 1..T (the safety
-  condition) and every robot within goal_tol of its goal at t = T (the terminal
-  condition read with a tolerance).
+  condition); Section V-A glosses a successful solution as feasible and
+  conflict-free, and feasibility holds by construction of the rollout.
+* at_goal: every robot within goal_tol of its goal at t = T (the terminal
+  condition read with a tolerance), reported beside success.
 * objective (Eq. objective): fraction of robot-steps t = 1..T within goal_tol.
 
 Pinned by brute-force pair loops on small teams, a closed-form head-on pass,
@@ -86,7 +88,7 @@ def reward(prob, x, goal, pred_dtype=np.float64):
 
 
 def success(prob, x, goal):
-    """Safety at t = 1..T (strict, 2 R_a) and terminal condition within goal_tol."""
+    """Safety at t = 1..T: every pair strictly farther apart than 2 R_a."""
     _, _, dp = dims(prob.dyn)
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[1]
@@ -94,11 +96,15 @@ def success(prob, x, goal):
     pt = np.moveaxis(pos, 2, 1)
     d = np.sqrt(pair_dist_sq(pt, np.float64))
     d = d + np.eye(n) * 1e30
-    safe = (d > 2.0 * float(np.float32(prob.robot_radius))).all(axis=(1, 2, 3))
+    return (d > 2.0 * float(np.float32(prob.robot_radius))).all(axis=(1, 2, 3))
+
+
+def at_goal(prob, x, goal):
+    """Terminal condition: every robot within goal_tol of its goal at t = T."""
+    _, _, dp = dims(prob.dyn)
+    x = np.asarray(x, dtype=np.float64)
     g = np.asarray(goal, dtype=np.float64)[None, :, :]
-    term = (np.linalg.norm(x[:, :, -1, :dp] - g, axis=-1)
-            <= float(np.float32(prob.goal_tol))).all(axis=1)
-    return safe & term
+    return (np.linalg.norm(x[:, :, -1, :dp] - g, axis=-1) <= float(np.float32(prob.goal_tol))).all(axis=1)
 
 
 def objective(prob, x, goal):

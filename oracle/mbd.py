@@ -110,6 +110,7 @@ def apply_deformation(prob, x0, goal, u_base, du0):
     r, hits, robots_hit = fitness.reward(prob, x, goal)
     return dict(u=u, x=x[0], r=float(r[0]), hits=int(hits[0]), robots_hit=int(robots_hit[0]),
                 success=bool(fitness.success(prob, x, goal)[0]),
+                at_goal=bool(fitness.at_goal(prob, x, goal)[0]),
                 objective=float(fitness.objective(prob, x, goal)[0]))
 
 

@@ -39,7 +39,7 @@ class D4Problem(ctypes.Structure):
 
 class D4Stats(ctypes.Structure):
     _fields_ = [("reward", c_float), ("objective", c_float), ("hits", c_int32),
-                ("robots_hit", c_int32), ("success", c_int32), ("status", c_int32)]
+                ("robots_hit", c_int32), ("success", c_int32), ("at_goal", c_int32), ("status", c_int32)]
 
 
 def _load():
@@ -230,7 +230,7 @@ class Context:
         torch.cuda.current_stream().synchronize()
         s = self._stats
         return dict(reward=s.reward, objective=s.objective, hits=s.hits, robots_hit=s.robots_hit,
-                    success=bool(s.success), status=s.status)
+                    success=bool(s.success), at_goal=bool(s.at_goal), status=s.status)
 
 
 def plan(p: Problem, x0, goal, iterations: int, u_init=None, stop_on_success=False):
@@ -254,7 +254,7 @@ def plan(p: Problem, x0, goal, iterations: int, u_init=None, stop_on_success=Fal
 
 def _stats_dict(s):
     return dict(reward=s.reward, objective=s.objective, hits=s.hits, robots_hit=s.robots_hit,
-                success=bool(s.success), status=s.status)
+                success=bool(s.success), at_goal=bool(s.at_goal), status=s.status)
 
 
 class BatchContext:

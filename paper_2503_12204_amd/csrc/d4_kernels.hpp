@@ -749,7 +749,7 @@ struct FinalArgs {
     const float* x0;      // [n][dx]
     const float* goal;    // [n][dp]
     float* traj;          // [n][T+1][dx]
-    float* stats;         // d4_stats layout: reward, objective, hits, robots_hit, success, status
+    float* stats;         // d4_stats layout: reward, objective, hits, robots_hit, success, at_goal, status
     const int* status;    // sticky status of the iteration
     int n, T;
     float ulo[3], uhi[3];
@@ -826,7 +826,7 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
     red_s[tid] = safe_cnt;
     red_h[tid] = hit_cnt;
     red_o[tid] = at_goal;
-    red_bad[tid] = unsafe | term_bad;
+    red_bad[tid] = unsafe | (term_bad << 1);
     __syncthreads();
     if (tid == 0) {
         float gs = 0.0f;
@@ -844,8 +844,9 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
         int* si = reinterpret_cast<int*>(a.stats);
         si[2] = hs;
         si[3] = ss;
-        si[4] = bad ? 0 : 1;
-        si[5] = a.status ? *a.status : 0;
+        si[4] = (bad & 1) ? 0 : 1;
+        si[5] = (bad & 2) ? 0 : 1;
+        si[6] = a.status ? *a.status : 0;
     }
 }
 
@@ -989,7 +990,7 @@ struct BatchFinalArgs {
     const float* x0;
     const float* goal;
     float* traj;
-    float* stats;        // [count][6]
+    float* stats;        // [count][7], d4_stats layout
     const int* status;   // [count]
     uint32_t flags;
 };
@@ -1003,7 +1004,7 @@ static __global__ void __launch_bounds__(256) k_batch_final(const BatchFinalArgs
     a.x0 = b.x0 + in.x0;
     a.goal = b.goal + in.goal;
     a.traj = b.traj + in.traj;
-    a.stats = b.stats + 6 * (size_t)blockIdx.x;
+    a.stats = b.stats + 7 * (size_t)blockIdx.x;
     a.status = b.status + blockIdx.x;
     a.n = in.n;
     a.T = in.T;

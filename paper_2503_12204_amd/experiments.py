@@ -126,6 +126,8 @@ def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=
                                    "proposal": [float(np.mean([s["reward"] for s in it])) for it in hist_n]},
         "success_after_iteration": {"plain": [float(np.mean([s["success"] for s in it])) for it in hist_p],
                                     "proposal": [float(np.mean([s["success"] for s in it])) for it in hist_n]},
+        "at_goal_after_iteration": {"plain": [float(np.mean([s["at_goal"] for s in it])) for it in hist_p],
+                                    "proposal": [float(np.mean([s["at_goal"] for s in it])) for it in hist_n]},
         "iterations_to_target_mean": {"plain": kp_mean, "proposal": kn_mean},
         "target_reached_fraction": {"plain": 1.0, "proposal": float(reach_n.mean())},
         "iterations_to_first_success_mean": {"plain": float(succ_p.mean()), "proposal": float(succ_n.mean())},

@@ -245,6 +245,7 @@ def test_denoise_iteration_chain_and_graph(L):
         fin = ombd.apply_deformation(p, x0, g, u_base, _np(du0))
         assert abs(st["reward"] - fin["r"]) <= FINAL_RTOL * abs(fin["r"])
         assert st["hits"] == fin["hits"] and st["success"] == fin["success"]
+        assert st["at_goal"] == fin["at_goal"]
         assert abs(st["objective"] - fin["objective"]) < 1e-6  # FP32 ratio of counts
         assert np.allclose(_np(traj), fin["x"], rtol=0, atol=2e-6 * p.horizon * 5)
 

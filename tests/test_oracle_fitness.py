@@ -145,6 +145,7 @@ def test_success_and_objective():
     x[2, 1, -1, 0] = -0.8           # terminal miss
     x[:, 1, -1, 1] = 0.0
     s = fitness.success(p, x, goal)
-    assert list(s) == [True, False, False]
+    assert list(s) == [True, False, True]
+    assert list(fitness.at_goal(p, x, goal)) == [True, True, False]
     o = fitness.objective(p, x, goal)
     assert abs(o[0] - 2 / 8) < 1e-15 and abs(o[2] - 1 / 8) < 1e-15
