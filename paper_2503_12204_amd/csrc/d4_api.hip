@@ -78,8 +78,8 @@ int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStre
 
 // Weighted update of step i: softmax weights from the reward statistics, the
 // weighted sum of the draws and the rescaled deformation.
-int launch_update(const d4_problem* p, const float* eps, const float* r, const float* du_in, float* du_out, float* w_out, int* status, float ms, float sigma,
-                  float os, hipStream_t st) {
+int launch_update(const d4_problem* p, const float* eps, const float* r, const float* du_in, float* du_out,
+                  float* w_out, int* status, float ms, float sigma, float os, hipStream_t st) {
     const int D = p->n_robots * p->horizon * shape_of(p->dyn).du;
     const int M = p->n_samples;
     if (M > 16384) return fail(D4_EUNSUPPORTED, "n_samples %d above the 16384 weights one workgroup stages", M);
@@ -97,17 +97,23 @@ int launch_update(const d4_problem* p, const float* eps, const float* r, const f
     a.ms = ms;
     a.sigma = sigma;
     a.os = os;
-    const bool vec = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(eps) & 15u) == 0);
-    const int waves = 4;
-    int grid = (D + waves - 1) / waves;
-    int cap = 1024;
-    if (const char* e = std::getenv("D4_UPD_GRID")) cap = std::max(1, std::atoi(e));
-    if (grid > cap) grid = cap;
-    const size_t lds = (size_t)M * 4;
-    if (vec)
-        hipLaunchKernelGGL((k_softmax_update<true>), dim3(grid), dim3(64 * waves), lds, st, a);
-    else
-        hipLaunchKernelGGL((k_softmax_update<false>), dim3(grid), dim3(64 * waves), lds, st, a);
+    // register form when the rows are whole float4s; LDS form otherwise
+    const int J = upd_reg_j(M, eps, r);
+    if (J > 0) {
+        int grid = std::max(1, std::min(512, (D + UPD_ROWS - 1) / UPD_ROWS));
+        if (const char* e = std::getenv("D4_UPD_GRID")) grid = std::max(1, std::min(D, std::atoi(e)));
+        switch (J) {
+            case 1: hipLaunchKernelGGL(k_softmax_update_reg<1>, dim3(grid), dim3(256), 0, st, a); break;
+            case 2: hipLaunchKernelGGL(k_softmax_update_reg<2>, dim3(grid), dim3(256), 0, st, a); break;
+            case 4: hipLaunchKernelGGL(k_softmax_update_reg<4>, dim3(grid), dim3(256), 0, st, a); break;
+            case 8: hipLaunchKernelGGL(k_softmax_update_reg<8>, dim3(grid), dim3(256), 0, st, a); break;
+            default: hipLaunchKernelGGL(k_softmax_update_reg<16>, dim3(grid), dim3(256), 0, st, a); break;
+        }
+    } else {
+        const int waves = 4;
+        int grid = std::min(1024, (D + waves - 1) / waves);
+        hipLaunchKernelGGL(k_softmax_update, dim3(grid), dim3(64 * waves), (size_t)M * 4, st, a);
+    }
     HIP_LAUNCH_CHECK("k_softmax_update");
     return D4_OK;
 }

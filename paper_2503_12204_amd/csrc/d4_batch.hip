@@ -101,10 +101,15 @@ int enqueue_batch_iteration(d4_batch* b, hipStream_t st) {
         ua.ms = sc.ms[i];
         ua.sigma = sc.sigma[i];
         ua.os = sc.os[i];
-        if (M % 4 == 0)
-            hipLaunchKernelGGL(k_batch_update<true>, dim3((unsigned)b->rows.size()), dim3(256), (size_t)M * 4, st, ua);
-        else
-            hipLaunchKernelGGL(k_batch_update<false>, dim3((unsigned)b->rows.size()), dim3(256), (size_t)M * 4, st, ua);
+        const dim3 ng((unsigned)b->rows.size());
+        switch (upd_reg_j(M, b->eps, b->r)) {
+            case 0: hipLaunchKernelGGL(k_batch_update<0>, ng, dim3(256), (size_t)M * 4, st, ua); break;
+            case 1: hipLaunchKernelGGL(k_batch_update<1>, ng, dim3(256), 0, st, ua); break;
+            case 2: hipLaunchKernelGGL(k_batch_update<2>, ng, dim3(256), 0, st, ua); break;
+            case 4: hipLaunchKernelGGL(k_batch_update<4>, ng, dim3(256), 0, st, ua); break;
+            case 8: hipLaunchKernelGGL(k_batch_update<8>, ng, dim3(256), 0, st, ua); break;
+            default: hipLaunchKernelGGL(k_batch_update<16>, ng, dim3(256), 0, st, ua); break;
+        }
         HIP_LAUNCH_CHECK("k_batch_update");
         std::swap(du_cur, du_nxt);
     }

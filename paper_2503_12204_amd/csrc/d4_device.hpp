@@ -36,8 +36,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // three-input XORs (truth table 0x96) in one gfx950 instruction each
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -183,10 +184,17 @@ __device__ __forceinline__ float goal_term(float dist, float inv_d0) {
     return __builtin_fmaf(-dist, inv_d0, 1.0f);
 }
 
-// Sampled control clip(u_base + du * mean_scale + sigma * eps) of one element.
+// Sampled control clip(u_base + du * mean_scale + sigma * eps) of one element,
+// in two parts: the sample mean u_base + du * mean_scale, then the draw.
+__device__ __forceinline__ float sample_mean(float ub, float du, float mscale) {
+    return __builtin_fmaf(du, mscale, ub);
+}
+__device__ __forceinline__ float sample_from_mean(float mean, float sigma, float z, float lo, float hi) {
+    return fminf(fmaxf(__builtin_fmaf(sigma, z, mean), lo), hi);
+}
 __device__ __forceinline__ float sample_control(float ub, float du, float mscale, float sigma, float z, float lo,
                                                 float hi) {
-    return fminf(fmaxf(__builtin_fmaf(sigma, z, __builtin_fmaf(du, mscale, ub)), lo), hi);
+    return sample_from_mean(sample_mean(ub, du, mscale), sigma, z, lo, hi);
 }
 
 // Team reward (sum of goal terms - w_safe * penalty) / (n T).

@@ -235,6 +235,17 @@ inline size_t rollfit_lds(const d4_problem* p, Tile t) {
     return a > b ? a : b;
 }
 
+// Float4 columns per lane of the register form of the update kernel (the
+// smallest power of two with 1024 J >= M), or 0 for the LDS form: the sample
+// count must be a multiple of 4 and the draws and rewards 16-byte aligned.
+inline int upd_reg_j(int M, const void* eps, const void* r) {
+    if (M % 4 || M > 16384 || (reinterpret_cast<uintptr_t>(eps) & 15u) || (reinterpret_cast<uintptr_t>(r) & 15u))
+        return 0;
+    int J = 1;
+    while (J * 1024 < M) J <<= 1;
+    return J;
+}
+
 // Whether every robot's draws start on a Philox block boundary.
 inline bool draws_aligned(const d4_problem* p) { return (p->horizon * shape_of(p->dyn).du) % 4 == 0; }
 

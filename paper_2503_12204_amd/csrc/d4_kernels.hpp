@@ -240,17 +240,22 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     };
 
     // control bases (u_base, du_in) of the next draw chunk, loaded one chunk
-    // ahead so that their latency hides behind the current chunk's draws
+    // ahead so that their latency hides behind the current chunk's draws.
+    // Buffer loads are range-checked against the D-element arrays (reads past
+    // the end return 0), so a chunk's loads need no guard: elements past the
+    // robot's last step belong to the next robot or are zero, and go unused.
     constexpr int CS = Chunk<DU>::STEPS, CG = Chunk<DU>::GROUPS, NE = 4 * CG;
     float ub_nx[NE], du_nx[NE];
+    const __amdgpu_buffer_rsrc_t ub_rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.u_base), (short)0, (int)(Dt * 4), 0x00020000);
+    const __amdgpu_buffer_rsrc_t du_rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.du_in), (short)0, (int)(Dt * 4), 0x00020000);
     auto load_ctrl = [&](int t) {
-        const int ne = min(CS, T - t) * DU;
-        const float* ubp = a.u_base + ebase + (uint32_t)(t * DU);
-        const float* dup = a.du_in + ebase + (uint32_t)(t * DU);
+        const int vo = (int)((ebase + (uint32_t)(t * DU)) * 4u);
 #pragma unroll
         for (int j = 0; j < NE; ++j) {
-            ub_nx[j] = j < ne ? ubp[j] : 0.0f;
-            du_nx[j] = j < ne ? dup[j] : 0.0f;
+            ub_nx[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ub_rs, vo + 4 * j, 0, 0));
+            du_nx[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(du_rs, vo + 4 * j, 0, 0));
         }
     };
     if (!FROM_X) load_ctrl(0);
@@ -273,13 +278,11 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                 const int t = t0 + tc;
                 const uint32_t e0 = ebase + (uint32_t)(t * DU);
                 const uint32_t g0 = e0 >> 2;
-                float ub_c[NE], du_c[NE];
+                // sample means of this chunk, then the next chunk's loads
+                float mean_c[NE];
 #pragma unroll
-                for (int j = 0; j < NE; ++j) {
-                    ub_c[j] = ub_nx[j];
-                    du_c[j] = du_nx[j];
-                }
-                if (t + CS < T) load_ctrl(t + CS);
+                for (int j = 0; j < NE; ++j) mean_c[j] = sample_mean(ub_nx[j], du_nx[j], mscale);
+                load_ctrl(t + CS);
                 float win[4 + 4 * CG];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) win[j] = left[j];
@@ -318,8 +321,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                         float u[DU];
 #pragma unroll
                         for (int d = 0; d < DU; ++d) {
-                            u[d] = sample_control(ub_c[s * DU + d], du_c[s * DU + d], mscale, sigma,
-                                                  z[s * DU + d], ulo[d], uhi[d]);
+                            u[d] = sample_from_mean(mean_c[s * DU + d], sigma, z[s * DU + d], ulo[d], uhi[d]);
                         }
                         DY::step(x, aux, u, a.sc);
                         after_step(tc + s);
@@ -644,27 +646,20 @@ __device__ __forceinline__ void block_sum_max(float& s, float& mx, float* red) {
 }
 
 // Softmax weights (Section IV-B, p_0 proportional to exp(r/lambda) of the
-// batch-normalised rewards) and the one-step update (Eq. mbd-denoising):
-// every workgroup stages the rewards in LDS, takes their mean, population
-// variance and maximum in a fixed order (two passes), replaces them by the
-// unnormalised weights exp(z_m - z_max) with their sum, then reduces rows of
-// eps, one wave per row, and applies the normaliser once per row.  All
-// workgroups of one launch (and of the batched form, which uses the same
-// 256-lane workgroups) compute the same weights bit for bit.
-template <bool VEC>
+// batch-normalised rewards) and the one-step update (Eq. mbd-denoising), for
+// any sample count: every workgroup stages the rewards in LDS, takes their
+// mean, population variance and maximum in a fixed order (two passes),
+// replaces them by the unnormalised weights exp(z_m - z_max) with their sum,
+// then reduces rows of eps, one wave per row, and applies the normaliser
+// once per row.  All workgroups of one launch (and of the batched form, which
+// uses the same 256-lane workgroups) compute the same weights bit for bit.
 __device__ __forceinline__ void softmax_update_rows(const UpdateArgs& a, int e_begin, int e_step, int e_end,
                                                     bool first, float* wl) {
 #pragma clang fp contract(off)
     __shared__ float red[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, bd = blockDim.x;
     const int M = a.M;
-    typedef float f4 __attribute__((ext_vector_type(4)));
-    if (VEC) {
-        const f4* r4 = reinterpret_cast<const f4*>(a.r);
-        for (int i = tid; i < (M >> 2); i += bd) reinterpret_cast<f4*>(wl)[i] = r4[i];
-    } else {
-        for (int i = tid; i < M; i += bd) wl[i] = a.r[i];
-    }
+    for (int i = tid; i < M; i += bd) wl[i] = a.r[i];
     __syncthreads();
     float sum = 0.0f, mx = -INFINITY;
     for (int i = tid; i < M; i += bd) {
@@ -703,34 +698,171 @@ __device__ __forceinline__ void softmax_update_rows(const UpdateArgs& a, int e_b
     for (int e = e_begin + wave; e < e_end; e += e_step) {
         const float* row = a.eps + (size_t)e * M;
         float acc = 0.0f;
-        if (VEC) {
-            const f4* r4 = reinterpret_cast<const f4*>(row);
-            const f4* w4 = reinterpret_cast<const f4*>(wl);
-            const int M4 = M >> 2;
-            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
-#pragma unroll 8
-            for (int i = lane; i < M4; i += 64) {
-                const f4 x = __builtin_nontemporal_load(r4 + i);
-                const f4 b = w4[i];
-                c0 = __builtin_fmaf(x.x, b.x, c0);
-                c1 = __builtin_fmaf(x.y, b.y, c1);
-                c2 = __builtin_fmaf(x.z, b.z, c2);
-                c3 = __builtin_fmaf(x.w, b.w, c3);
-            }
-            acc = (c0 + c1) + (c2 + c3);
-        } else {
-            for (int i = lane; i < M; i += 64) acc = __builtin_fmaf(row[i], wl[i], acc);
-        }
+        for (int i = lane; i < M; i += 64) acc = __builtin_fmaf(row[i], wl[i], acc);
         acc = wave_sum(acc);
         if (lane == 0) a.du_out[e] = a.os * (a.du_in[e] * a.ms + s_inv * acc);
     }
 }
 
-template <bool VEC>
-__global__ void __launch_bounds__(256) k_softmax_update(const UpdateArgs a) {
+static __global__ void __launch_bounds__(256) k_softmax_update(const UpdateArgs a) {
     extern __shared__ float wl[];
     const int nw = blockDim.x >> 6;
-    softmax_update_rows<VEC>(a, blockIdx.x * nw, gridDim.x * nw, a.D, blockIdx.x == 0, wl);
+    softmax_update_rows(a, blockIdx.x * nw, gridDim.x * nw, a.D, blockIdx.x == 0, wl);
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Range-checked 16-byte buffer load: bytes past num_records read as zero.
+__device__ __forceinline__ f4v load4_checked(__amdgpu_buffer_rsrc_t rs, int byte_offset) {
+    return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_offset, 0, 0));
+}
+
+// The same update for a sample count that is a multiple of 4, with the
+// weights in registers: lane t of the 256-lane workgroup owns the float4
+// columns t + 256 j (j < J, J * 1024 >= M) of the rewards, the weights and of
+// every eps row.  The workgroup handles rows e0 .. e1-1, UPD_ROWS at a time;
+// the first rows' loads are issued before the statistics so that their
+// latency overlaps the softmax.  Loads are range-checked buffer loads (columns
+// past M read as zero and carry weight zero), so no load needs a guard.
+// Statistics are taken per lane over its columns in j order, then across the
+// wave and the workgroup in a fixed order: every workgroup (of this launch
+// and of the batched form) computes the same weights bit for bit.
+constexpr int UPD_ROWS = 2;
+
+__device__ __forceinline__ float block_sum4(float s, float* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    s = wave_sum(s);
+    __syncthreads();
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+__device__ __forceinline__ float block_max4(float s, float* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    s = wave_max(s);
+    __syncthreads();
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+template <int J>
+__device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0, int e1, bool first) {
+#pragma clang fp contract(off)
+    __shared__ float red[4];
+    __shared__ float rowred[UPD_ROWS][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int M = a.M, M4 = M >> 2;
+    const __amdgpu_buffer_rsrc_t r_rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.r), (short)0, M * 4, 0x00020000);
+    f4v w[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) w[j] = load4_checked(r_rs, (tid + 256 * j) * 16);
+    f4v x[UPD_ROWS][J];
+    auto load_rows = [&](int e) {
+#pragma unroll
+        for (int q = 0; q < UPD_ROWS; ++q) {
+            const int ee = min(e + q, e1 - 1);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(a.eps + (size_t)ee * M), (short)0, M * 4, 0x00020000);
+#pragma unroll
+            for (int j = 0; j < J; ++j) x[q][j] = load4_checked(rs, (tid + 256 * j) * 16);
+        }
+    };
+    if (e0 < e1) load_rows(e0);
+    float sum = 0.0f, mx = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (tid + 256 * j < M4) {
+            sum += w[j].x;
+            sum += w[j].y;
+            sum += w[j].z;
+            sum += w[j].w;
+            mx = fmaxf(fmaxf(mx, fmaxf(w[j].x, w[j].y)), fmaxf(w[j].z, w[j].w));
+        }
+    }
+    sum = block_sum4(sum, red);
+    mx = block_max4(mx, red);
+    const float mean = sum / (float)M;
+    float q = 0.0f;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (tid + 256 * j < M4) {
+            float d = w[j].x - mean;
+            q = __builtin_fmaf(d, d, q);
+            d = w[j].y - mean;
+            q = __builtin_fmaf(d, d, q);
+            d = w[j].z - mean;
+            q = __builtin_fmaf(d, d, q);
+            d = w[j].w - mean;
+            q = __builtin_fmaf(d, d, q);
+        }
+    }
+    q = block_sum4(q, red);
+    const bool bad = !isfinite(mean) || !isfinite(q) || !isfinite(mx);
+    float mu = 0.0f, scale = a.inv_lam;
+    if (a.normalize) {
+        mu = mean;
+        scale = a.inv_lam / fmaxf(sqrtf(q / (float)M), 1e-6f);
+    }
+    const float zmax = (mx - mu) * scale;
+    float se = 0.0f;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const bool in = tid + 256 * j < M4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float e = !in ? 0.0f : bad ? 1.0f : __expf(__builtin_fmaf(w[j][c] - mu, scale, -zmax));
+            w[j][c] = e;
+            se += e;
+        }
+    }
+    se = block_sum4(se, red);
+    const float inv_se = 1.0f / se;
+    if (first) {
+        if (a.w_out) {
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                if (tid + 256 * j < M4)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) a.w_out[4 * (tid + 256 * j) + c] = w[j][c] * inv_se;
+        }
+        if (bad && tid == 0 && a.status) *a.status = -4;
+    }
+    const float s_inv = a.sigma * inv_se;
+    for (int e = e0; e < e1; e += UPD_ROWS) {
+        if (e != e0) load_rows(e);
+        float acc[UPD_ROWS];
+#pragma unroll
+        for (int rr = 0; rr < UPD_ROWS; ++rr) {
+            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                c0 = __builtin_fmaf(x[rr][j].x, w[j].x, c0);
+                c1 = __builtin_fmaf(x[rr][j].y, w[j].y, c1);
+                c2 = __builtin_fmaf(x[rr][j].z, w[j].z, c2);
+                c3 = __builtin_fmaf(x[rr][j].w, w[j].w, c3);
+            }
+            acc[rr] = wave_sum((c0 + c1) + (c2 + c3));
+        }
+        __syncthreads();
+        if (lane == 0)
+#pragma unroll
+            for (int rr = 0; rr < UPD_ROWS; ++rr) rowred[rr][wave] = acc[rr];
+        __syncthreads();
+        if (tid < UPD_ROWS && e + tid < e1) {
+            const float t = (rowred[tid][0] + rowred[tid][1]) + (rowred[tid][2] + rowred[tid][3]);
+            a.du_out[e + tid] = a.os * (a.du_in[e + tid] * a.ms + s_inv * t);
+        }
+    }
+}
+
+// Rows split evenly over the grid.
+template <int J>
+__global__ void __launch_bounds__(256) k_softmax_update_reg(const UpdateArgs a) {
+    const int e0 = (int)((long long)a.D * blockIdx.x / gridDim.x);
+    const int e1 = (int)((long long)a.D * (blockIdx.x + 1) / gridDim.x);
+    softmax_update_block<J>(a, e0, e1, blockIdx.x == 0);
 }
 
 static __global__ void k_fill(float* p, int n, float v) {
@@ -959,9 +1091,9 @@ struct BatchUpdArgs {
     float ms, sigma, os;
 };
 
-// Softmax weights and the update of one row range per workgroup (VEC: the
-// sample count is a multiple of 4, so rows are 16-byte aligned).
-template <bool VEC>
+// Softmax weights and the update of one row range per workgroup: the
+// register form (J > 0, sample count a multiple of 4) or the LDS form (J = 0).
+template <int J>
 __global__ void __launch_bounds__(256) k_batch_update(const BatchUpdArgs b) {
     extern __shared__ float wl[];
     const BatchRows rt = b.rows[blockIdx.x];
@@ -980,7 +1112,10 @@ __global__ void __launch_bounds__(256) k_batch_update(const BatchUpdArgs b) {
     a.ms = b.ms;
     a.sigma = b.sigma;
     a.os = b.os;
-    softmax_update_rows<VEC>(a, rt.e0, blockDim.x >> 6, rt.e1, rt.e0 == 0, wl);
+    if constexpr (J > 0)
+        softmax_update_block<J>(a, rt.e0, rt.e1, rt.e0 == 0);
+    else
+        softmax_update_rows(a, rt.e0, blockDim.x >> 6, rt.e1, rt.e0 == 0, wl);
 }
 
 struct BatchFinalArgs {
