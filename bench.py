@@ -191,6 +191,30 @@ def time_fused_kernel_in_iteration(L, p, x0, g, u, iteration):
     return e0.elapsed_time(e1) / len(steps) * 1e-3
 
 
+def time_update_kernel(L, p, x0, g, u, iteration, reps=20):
+    """Average duration of the update kernel (statistics, softmax, weighted
+    row reduction) on one step's draws and rewards, launched back to back
+    between HIP events on the launch stream."""
+    import torch
+    D, M = p.D, p.n_samples
+    eps = torch.empty((D, M), dtype=torch.float32, device="cuda")
+    r = torch.empty(M, dtype=torch.float32, device="cuda")
+    hits = torch.empty(M, dtype=torch.int32, device="cuda")
+    du = torch.zeros(D, dtype=torch.float32, device="cuda")
+    du_out = torch.empty(D, dtype=torch.float32, device="cuda")
+    w = torch.empty(M, dtype=torch.float32, device="cuda")
+    L.sample_rollout_fitness(p, x0, g, u.reshape(-1).contiguous(), du, iteration, p.n_steps, eps, r, hits)
+    L.score_update(p, r, eps, du, p.n_steps, du_out, w)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        L.score_update(p, r, eps, du, p.n_steps, du_out, w)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,8 +274,17 @@ def main():
     g = torch.as_tensor(gn, device="cuda")
 
     if args.kernel_only:
-        print(f"fused kernel x{args.kernel_only} on {args.workload}", flush=True)
+        print(f"fused kernel and update kernel x{args.kernel_only} on {args.workload}", flush=True)
         time_fused_kernel(L, p, x0, g, reps=args.kernel_only)
+        D, M = p.D, p.n_samples
+        eps = torch.empty((D, M), dtype=torch.float32, device="cuda")
+        r = torch.empty(M, dtype=torch.float32, device="cuda")
+        hits = torch.empty(M, dtype=torch.int32, device="cuda")
+        zero = torch.zeros(D, dtype=torch.float32, device="cuda")
+        L.sample_rollout_fitness(p, x0, g, zero, zero, 0, p.n_steps, eps, r, hits)
+        du_out = torch.empty(D, dtype=torch.float32, device="cuda")
+        for _ in range(args.kernel_only):
+            L.score_update(p, r, eps, zero, p.n_steps, du_out, None)
         n_bytes = 256 << 20
         a = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -287,6 +320,13 @@ def main():
                 "kernel": "k_rollfit (fused sample+rollout+reward)", "kernel_us": t_k * 1e6,
                 "ops_per_unit": opu, "tile": {"samples_per_group": S_t, "steps_per_block": Tb_t,
                                               "replicas": R_t}}
+    # the weighted reduction: HBM-bound; algorithmic bytes = the draws read
+    # once, the rewards, Delta U in and out, and the weights written once
+    t_u = time_update_kernel(L, p, x0, g, u, args.warmup + args.steps + 2)
+    upd_bytes = 4 * (p.D * p.n_samples + 2 * p.n_samples + 2 * p.D)
+    update = {"bound": "hbm", "achieved": upd_bytes / t_u / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": upd_bytes / t_u / 1e9 / HBM_PEAK_GBS, "kernel": "k_softmax_update (statistics, softmax, "
+              "weighted row reduction, update)", "kernel_us": t_u * 1e6, "bytes_per_launch": upd_bytes}
     out = {
         "metric": "robot*step*samples/s in rollout+fitness (whole denoising iteration)",
         "value": value, "unit": "robot*step*samples/s", "n_gpus": 1, "steps": args.steps,
@@ -296,6 +336,7 @@ def main():
                    "robots": p.n_robots, "horizon": p.horizon, "samples": p.n_samples,
                    "denoising_steps": p.n_steps, "dynamics": W.DYN_NAMES[p.dyn]},
         "roofline": roofline,
+        "update_kernel_roofline": update,
         "last_iteration": {"reward": st["reward"], "hits": st["hits"], "success": st["success"],
                            "at_goal": st["at_goal"]},
     }

@@ -6,8 +6,9 @@ batched_vs_plain: many uneven instances, one batched iteration against the
     (identical results, so time-to-target is the time for the same work).
 proposal_gain: train the proposal on teams the planner solved, then run the
     plain planner from zero controls and from the judged proposal on
-    held-out teams; an instance's target is the reward the plain planner
-    reaches with its full iteration budget.
+    held-out teams; an instance's target is 99.5 % of the reward the plain
+    planner reaches with its full iteration budget (the budget's reward
+    itself is reported as the strict target).
 """
 from __future__ import annotations
 
@@ -61,7 +62,7 @@ def _chunks(seq, k):
 
 
 def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=3, eval_samples=2048,
-                  eval_iters=5, epochs=20, seed=0, log=print):
+                  eval_iters=5, epochs=20, seed=0, target_tol=0.005, log=print):
     rng = np.random.default_rng(1_000_000 + seed)
     t0 = time.perf_counter()
     train = [PR.random_team(rng, n_samples=label_samples, instance_id=j) for j in range(n_train)]
@@ -103,19 +104,31 @@ def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=
     hist_p = [sum((h[k] for h in hp), []) for k in range(eval_iters)]
     hist_n = [sum((h[k] for h in hn), []) for k in range(eval_iters)]
     t_iter = sum(tp) / n_test       # seconds of batched iteration per team
-    target = np.array([s["reward"] for s in hist_p[-1]])
+    final = np.array([s["reward"] for s in hist_p[-1]])
+    # target: 99.5 % of the reward the plain planner reaches with its full
+    # budget (the strict target, its final reward itself, is reported too: it
+    # is a noisy maximum that the plain planner meets by construction)
+    target = final - target_tol * np.abs(final)
     k_p = PR.iterations_to_target(hist_p, target)
     k_n = PR.iterations_to_target(hist_n, target, init_rewards=r_init)
+    reach_p = k_p <= eval_iters
     reach_n = k_n <= eval_iters
+    k_p_strict = PR.iterations_to_target(hist_p, final)
+    k_n_strict = PR.iterations_to_target(hist_n, final, init_rewards=r_init)
     succ_p = PR.iterations_to_target([[{"reward": float(s["success"])} for s in it] for it in hist_p],
                                      np.ones(n_test))
     succ_n = PR.iterations_to_target([[{"reward": float(s["success"])} for s in it] for it in hist_n],
                                      np.ones(n_test))
-    kp_mean = float(k_p.mean())
-    kn_eff = np.where(reach_n, k_n, eval_iters + 1)
-    kn_mean = float(kn_eff.mean())
+    kp_mean = float(np.where(reach_p, k_p, eval_iters + 1).mean())
+    kn_mean = float(np.where(reach_n, k_n, eval_iters + 1).mean())
     t_plain = kp_mean * t_iter
     t_net = kn_mean * t_iter + t_infer / n_test
+    kps = float(np.minimum(k_p_strict, eval_iters + 1).mean())
+    kns = float(np.minimum(k_n_strict, eval_iters + 1).mean())
+    strict = {"iterations_to_target_mean": {"plain": kps, "proposal": kns},
+              "target_reached_fraction": {"plain": float((k_p_strict <= eval_iters).mean()),
+                                          "proposal": float((k_n_strict <= eval_iters).mean())},
+              "time_to_target_speedup": (kps * t_iter) / (kns * t_iter + t_infer / n_test)}
     out = {
         "train_teams": n_train, "test_teams": n_test, "label_samples": label_samples, "label_iterations": label_iters,
         "eval_samples": eval_samples, "eval_iterations": eval_iters, "epochs": epochs,
@@ -128,8 +141,10 @@ def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=
                                     "proposal": [float(np.mean([s["success"] for s in it])) for it in hist_n]},
         "at_goal_after_iteration": {"plain": [float(np.mean([s["at_goal"] for s in it])) for it in hist_p],
                                     "proposal": [float(np.mean([s["at_goal"] for s in it])) for it in hist_n]},
+        "target": f"{100 * (1 - target_tol):.1f} % of the plain planner's reward after {eval_iters} iterations",
         "iterations_to_target_mean": {"plain": kp_mean, "proposal": kn_mean},
-        "target_reached_fraction": {"plain": 1.0, "proposal": float(reach_n.mean())},
+        "target_reached_fraction": {"plain": float(reach_p.mean()), "proposal": float(reach_n.mean())},
+        "strict_target": strict,
         "iterations_to_first_success_mean": {"plain": float(succ_p.mean()), "proposal": float(succ_n.mean())},
         "seconds_per_iteration_per_team": t_iter, "proposal_inference_seconds_per_team": t_infer / n_test,
         "time_to_target_seconds_per_team": {"plain": t_plain, "proposal": t_net},
