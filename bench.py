@@ -43,7 +43,8 @@ HBM_PEAK_GBS = 8000.0
 #    products 2 = 64 per pair (32); 44.5 per normal in all
 #  - sampled control: fma, fma, max, min = 4 per component
 #  - dynamics per step: double integrator 5 per axis; unicycle 13 (two heading
-#    updates, two hardware sin/cos pairs, Simpson sums)
+#    updates, two hardware sin/cos pairs, Simpson sums); differential drive 17
+#    (the unicycle's plus the speed's two fused steps and its clip)
 #  - goal term: 2 d_p + 3 (squared distance, square root, fused step, sum)
 #  - bounding box of the block: 2 d_p
 #  - broad phase: (n - 1)/2 partners per robot and block of Tb steps, 4 d_p + 2
@@ -57,7 +58,7 @@ OPS_PER_NORMAL = 44.5
 def ops_per_unit(dyn, n, steps_per_block):
     from paper_2503_12204_amd import workloads as W
     dx, du, dp = W.dims(dyn)
-    dyn_ops = 13 if dyn == W.UNICYCLE else 5 * dp
+    dyn_ops = {W.UNICYCLE: 13, W.DIFFDRIVE: 17}.get(dyn, 5 * dp)
     broad = (n - 1) / 2.0 * (4 * dp + 2) / steps_per_block
     return du * OPS_PER_NORMAL + 4 * du + dyn_ops + (2 * dp + 3) + 2 * dp + broad + 3
 

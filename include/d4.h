@@ -39,8 +39,10 @@ enum {
     D4_EUNSUPPORTED = -5   /* shape beyond this build's limits */
 };
 
-/* Robot models (Section V; the unicycle is the 3-state differential drive). */
-enum { D4_HOLO2D = 0, D4_HOLO3D = 1, D4_UNICYCLE = 2 };
+/* Robot models (Section V).  HOLO2D/HOLO3D: x = [p, v], u = a.  UNICYCLE:
+ * x = [p_x, p_y, theta], u = [v, omega].  DIFFDRIVE, the paper's differential
+ * drive: x = [p_x, p_y, theta, v], u = [omega, a], speed clipped to v_max. */
+enum { D4_HOLO2D = 0, D4_HOLO3D = 1, D4_UNICYCLE = 2, D4_DIFFDRIVE = 3 };
 
 /* Flag bits of d4_problem.flags. */
 enum {
@@ -56,7 +58,7 @@ enum {
  * and Algorithm 1.
  */
 typedef struct d4_problem {
-    int32_t dyn;            /* D4_HOLO2D, D4_HOLO3D or D4_UNICYCLE */
+    int32_t dyn;            /* D4_HOLO2D, D4_HOLO3D, D4_UNICYCLE or D4_DIFFDRIVE */
     int32_t n_robots;       /* n, 1..32 */
     int32_t horizon;        /* T, >= 1 */
     int32_t n_samples;      /* M, >= 1 */
@@ -70,7 +72,7 @@ typedef struct d4_problem {
     float beta_max;         /* linear beta schedule, step N */
     float u_lo[3];          /* per-component control box */
     float u_hi[3];
-    float v_max;            /* per-component speed bound, holonomic models */
+    float v_max;            /* speed bound: per component (holonomic), |v| (DIFFDRIVE) */
     float goal_tol;         /* terminal-condition tolerance */
     float d0_floor;         /* floor of the r_goal denominator */
     uint32_t flags;         /* D4_NORMALIZE | D4_SAFE_PAIRS */

@@ -8,24 +8,29 @@ state this way.  Models (Section V and the workload definitions):
 * HOLO2D: x = [p_x, p_y, v_x, v_y], u = [a_x, a_y], f = [v, a]  (double integrator)
 * HOLO3D: the same in three dimensions
 * UNICYCLE: x = [p_x, p_y, theta], u = [v, omega], f = [v cos theta, v sin theta, omega]
+* DIFFDRIVE (the paper's differential drive, Section V): x = [p_x, p_y, theta, v],
+  u = [omega, a], f = [v cos theta, v sin theta, omega, a]
 
 Readings (the paper is silent on limits): every control component is clipped to
 [u_lo, u_hi] before it is applied; holonomic velocities are clipped per
-component to [-v_max, v_max] after each full RK4 step; theta is not wrapped.
+component, and the differential drive's speed v, to [-v_max, v_max] after each
+full RK4 step; theta is not wrapped.
 
 The RK4 step below is the literal four-stage formula; nothing is simplified.
 Pinned by closed forms: RK4 is exact for the double integrator, reduces to
 Simpson's rule for the unicycle, zero control keeps a resting team at rest,
-and translation equivariance (tests/test_oracle_dynamics.py).
+and translation equivariance; the differential drive reduces to Simpson's rule
+as well and is exact on straight lines at constant acceleration
+(tests/test_oracle_dynamics.py).
 """
 import numpy as np
 
-HOLO2D, HOLO3D, UNICYCLE = 0, 1, 2
+HOLO2D, HOLO3D, UNICYCLE, DIFFDRIVE = 0, 1, 2, 3
 
 
 def dims(dyn):
     """(d_x, d_u, d_p) of a dynamics id."""
-    return {HOLO2D: (4, 2, 2), HOLO3D: (6, 3, 3), UNICYCLE: (3, 2, 2)}[dyn]
+    return {HOLO2D: (4, 2, 2), HOLO3D: (6, 3, 3), UNICYCLE: (3, 2, 2), DIFFDRIVE: (4, 2, 2)}[dyn]
 
 
 def f_dyn(dyn, x, u):
@@ -36,6 +41,9 @@ def f_dyn(dyn, x, u):
     if dyn == UNICYCLE:
         v, om, th = u[..., 0], u[..., 1], x[..., 2]
         return np.stack([v * np.cos(th), v * np.sin(th), om], axis=-1)
+    if dyn == DIFFDRIVE:
+        om, a, th, v = u[..., 0], u[..., 1], x[..., 2], x[..., 3]
+        return np.stack([v * np.cos(th), v * np.sin(th), om, a], axis=-1)
     raise ValueError(dyn)
 
 
@@ -63,6 +71,9 @@ def step(prob, x, u):
         dp = dims(prob.dyn)[2]
         vm = float(prob.v_max)
         xn[..., dp:2 * dp] = np.minimum(np.maximum(xn[..., dp:2 * dp], -vm), vm)
+    elif prob.dyn == DIFFDRIVE:
+        vm = float(prob.v_max)
+        xn[..., 3] = np.minimum(np.maximum(xn[..., 3], -vm), vm)
     return xn
 
 

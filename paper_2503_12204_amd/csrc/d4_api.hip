@@ -58,9 +58,13 @@ int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStre
                 allow_lds(k_rollfit_coop<HOLO3D>, lds);
                 hipLaunchKernelGGL(k_rollfit_coop<HOLO3D>, grid, block, lds, st, a, tile.R);
                 break;
-            default:
+            case UNICYCLE:
                 allow_lds(k_rollfit_coop<UNICYCLE>, lds);
                 hipLaunchKernelGGL(k_rollfit_coop<UNICYCLE>, grid, block, lds, st, a, tile.R);
+                break;
+            default:
+                allow_lds(k_rollfit_coop<DIFFDRIVE>, lds);
+                hipLaunchKernelGGL(k_rollfit_coop<DIFFDRIVE>, grid, block, lds, st, a, tile.R);
                 break;
         }
         HIP_LAUNCH_CHECK("k_rollfit_coop");
@@ -70,7 +74,8 @@ int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStre
     switch (p->dyn) {
         case HOLO2D: launch_rollfit_dyn<HOLO2D>(FROM_X, al, grid, block, lds, st, a); break;
         case HOLO3D: launch_rollfit_dyn<HOLO3D>(FROM_X, al, grid, block, lds, st, a); break;
-        default: launch_rollfit_dyn<UNICYCLE>(FROM_X, al, grid, block, lds, st, a); break;
+        case UNICYCLE: launch_rollfit_dyn<UNICYCLE>(FROM_X, al, grid, block, lds, st, a); break;
+        default: launch_rollfit_dyn<DIFFDRIVE>(FROM_X, al, grid, block, lds, st, a); break;
     }
     HIP_LAUNCH_CHECK("k_rollfit");
     return D4_OK;
@@ -214,7 +219,8 @@ int enqueue_iteration(d4_ctx* c, hipStream_t st) {
     switch (p->dyn) {
         case HOLO2D: hipLaunchKernelGGL(k_apply_final<HOLO2D>, dim3(1), dim3(256), 0, st, f); break;
         case HOLO3D: hipLaunchKernelGGL(k_apply_final<HOLO3D>, dim3(1), dim3(256), 0, st, f); break;
-        default: hipLaunchKernelGGL(k_apply_final<UNICYCLE>, dim3(1), dim3(256), 0, st, f); break;
+        case UNICYCLE: hipLaunchKernelGGL(k_apply_final<UNICYCLE>, dim3(1), dim3(256), 0, st, f); break;
+        default: hipLaunchKernelGGL(k_apply_final<DIFFDRIVE>, dim3(1), dim3(256), 0, st, f); break;
     }
     HIP_LAUNCH_CHECK("k_apply_final");
     return D4_OK;
@@ -276,7 +282,8 @@ int32_t d4_rollout(const d4_problem* p, const float* x0, const float* u, float* 
     switch (p->dyn) {
         case HOLO2D: D4_ROLL(HOLO2D); break;
         case HOLO3D: D4_ROLL(HOLO3D); break;
-        default: D4_ROLL(UNICYCLE); break;
+        case UNICYCLE: D4_ROLL(UNICYCLE); break;
+        default: D4_ROLL(DIFFDRIVE); break;
     }
 #undef D4_ROLL
     HIP_LAUNCH_CHECK("k_rollout");
@@ -513,7 +520,7 @@ int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samp
     p.dyn = dyn;
     p.n_robots = n_robots;
     p.horizon = horizon;
-    if (dyn < 0 || dyn > 2 || n_robots < 1 || n_robots > 32 || horizon < 1)
+    if (dyn < 0 || dyn > 3 || n_robots < 1 || n_robots > 32 || horizon < 1)
         return fail(D4_EINVAL, "bad problem shape");
     Tile t;
     t.S = samples_per_group;

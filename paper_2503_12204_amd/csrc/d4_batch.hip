@@ -40,7 +40,7 @@ bool same_sampler(const d4_problem& a, const d4_problem& b) {
 // Relative cost of one reward tile: steps times the per-lane work of a step.
 double tile_cost(const d4_problem& p) {
     const Shape s = shape_of(p.dyn);
-    const double dyn_ops = p.dyn == UNICYCLE ? 13 : 5 * s.dp;
+    const double dyn_ops = p.dyn == UNICYCLE ? 13 : p.dyn == DIFFDRIVE ? 17 : 5 * s.dp;
     return (double)p.horizon * (s.du * 66.0 + dyn_ops + (2 * s.dp + 3) * (1 + (p.n_robots - 1) / 2.0) + 4);
 }
 

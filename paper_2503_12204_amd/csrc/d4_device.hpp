@@ -20,7 +20,7 @@
 
 namespace d4 {
 
-enum { HOLO2D = 0, HOLO3D = 1, UNICYCLE = 2 };
+enum { HOLO2D = 0, HOLO3D = 1, UNICYCLE = 2, DIFFDRIVE = 3 };
 enum { FLAG_NORMALIZE = 1, FLAG_SAFE_PAIRS = 2 };
 
 // ------------------------------------------------------------------ Philox
@@ -260,6 +260,39 @@ struct Dyn<UNICYCLE> {
         x[0] = __builtin_fmaf(kv, __builtin_fmaf(4.0f, ch, aux[0]) + c1, x[0]);
         x[1] = __builtin_fmaf(kv, __builtin_fmaf(4.0f, sh, aux[1]) + s1, x[1]);
         x[2] = th_1;
+        aux[0] = c1;
+        aux[1] = s1;
+    }
+};
+
+// The paper's differential drive (Section V): x = [p_x, p_y, theta, v],
+// u = [omega, a].  Within a step theta and v are linear in time, so the RK4
+// stages depend on time alone, k2 = k3, and the position update is Simpson's
+// rule on v(s) [cos, sin](theta(s)); theta and v themselves advance exactly.
+// The speed is clipped to [-v_max, v_max] after the step.
+template <>
+struct Dyn<DIFFDRIVE> {
+    static constexpr int DX = 4, DU = 2, DP = 2, AUX = 2;
+    // aux = (cos theta, sin theta) of the current heading
+    __device__ __forceinline__ static void init(const float* x, float* aux) {
+        __sincosf(x[2], &aux[1], &aux[0]);
+    }
+    __device__ __forceinline__ static void step(float* x, float* aux, const float* u,
+                                                const StepConsts& c) {
+#pragma clang fp contract(off)
+        const float om = u[0], acc = u[1];
+        const float th_h = __builtin_fmaf(om, c.hdt, x[2]);
+        const float th_1 = __builtin_fmaf(om, c.dt, x[2]);
+        float sh, ch, s1, c1;
+        __sincosf(th_h, &sh, &ch);
+        __sincosf(th_1, &s1, &c1);
+        const float v0 = x[3];
+        const float vh = __builtin_fmaf(acc, c.hdt, v0);
+        const float v1 = __builtin_fmaf(acc, c.dt, v0);
+        x[0] = __builtin_fmaf(c.dt6, __builtin_fmaf(4.0f * vh, ch, v0 * aux[0]) + v1 * c1, x[0]);
+        x[1] = __builtin_fmaf(c.dt6, __builtin_fmaf(4.0f * vh, sh, v0 * aux[1]) + v1 * s1, x[1]);
+        x[2] = th_1;
+        x[3] = fminf(fmaxf(v1, -c.vmax), c.vmax);
         aux[0] = c1;
         aux[1] = s1;
     }

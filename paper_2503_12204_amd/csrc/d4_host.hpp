@@ -54,7 +54,8 @@ inline Shape shape_of(int dyn) {
     switch (dyn) {
         case HOLO2D: return {4, 2, 2};
         case HOLO3D: return {6, 3, 3};
-        default: return {3, 2, 2};
+        case UNICYCLE: return {3, 2, 2};
+        default: return {4, 2, 2};
     }
 }
 
@@ -62,7 +63,7 @@ inline bool finite_f(float v) { return std::isfinite(v); }
 
 inline int validate(const d4_problem* p) {
     if (!p) return fail(D4_EINVAL, "problem is NULL");
-    if (p->dyn < 0 || p->dyn > 2) return fail(D4_EINVAL, "dyn %d is not a known model", p->dyn);
+    if (p->dyn < 0 || p->dyn > 3) return fail(D4_EINVAL, "dyn %d is not a known model", p->dyn);
     if (p->n_robots < 1 || p->n_robots > 32)
         return fail(D4_EINVAL, "n_robots %d outside 1..32", p->n_robots);
     if (p->horizon < 1) return fail(D4_EINVAL, "horizon %d < 1", p->horizon);

@@ -1070,9 +1070,13 @@ static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArg
             if (al) rollfit_tile<HOLO3D, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
             else rollfit_tile<HOLO3D, MODE_FUSED>(a, tl.m0, lds);
             break;
-        default:
+        case UNICYCLE:
             if (al) rollfit_tile<UNICYCLE, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
             else rollfit_tile<UNICYCLE, MODE_FUSED>(a, tl.m0, lds);
+            break;
+        default:
+            if (al) rollfit_tile<DIFFDRIVE, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
+            else rollfit_tile<DIFFDRIVE, MODE_FUSED>(a, tl.m0, lds);
             break;
     }
 }
@@ -1157,7 +1161,8 @@ static __global__ void __launch_bounds__(256) k_batch_final(const BatchFinalArgs
     switch (in.dyn) {
         case HOLO2D: apply_final_body<HOLO2D>(a); break;
         case HOLO3D: apply_final_body<HOLO3D>(a); break;
-        default: apply_final_body<UNICYCLE>(a); break;
+        case UNICYCLE: apply_final_body<UNICYCLE>(a); break;
+        default: apply_final_body<DIFFDRIVE>(a); break;
     }
 }
 

@@ -19,7 +19,8 @@ import numpy as np
 HOLO2D = 0
 HOLO3D = 1
 UNICYCLE = 2
-DYN_NAMES = {HOLO2D: "holo2d", HOLO3D: "holo3d", UNICYCLE: "unicycle"}
+DIFFDRIVE = 3
+DYN_NAMES = {HOLO2D: "holo2d", HOLO3D: "holo3d", UNICYCLE: "unicycle", DIFFDRIVE: "diffdrive"}
 
 # flag bits (same values as the C header)
 FLAG_NORMALIZE = 1     # z-score the rewards of one batch before the softmax
@@ -34,6 +35,8 @@ def dims(dyn: int) -> Tuple[int, int, int]:
         return 6, 3, 3
     if dyn == UNICYCLE:
         return 3, 2, 2
+    if dyn == DIFFDRIVE:
+        return 4, 2, 2
     raise ValueError(f"unknown dynamics id {dyn}")
 
 
@@ -116,12 +119,13 @@ def random_points(rng: np.random.Generator, n: int, dp: int, box: float,
 
 
 def make_states(dyn: int, start_pos: np.ndarray, goal_pos: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
-    """Full start states (velocity 0; unicycle heading toward its goal) and goal positions."""
+    """Full start states (velocity 0; unicycle and differential drive heading
+    toward the goal) and goal positions."""
     dx, _, dp = dims(dyn)
     n = start_pos.shape[0]
     x0 = np.zeros((n, dx), dtype=np.float64)
     x0[:, :dp] = start_pos
-    if dyn == UNICYCLE:
+    if dyn in (UNICYCLE, DIFFDRIVE):
         d = goal_pos - start_pos
         x0[:, 2] = np.arctan2(d[:, 1], d[:, 0])
     return x0.astype(np.float32), goal_pos.astype(np.float32)
@@ -151,6 +155,23 @@ def unicycle_random(n: int = 8, horizon: int = 100, n_samples: int = 2048, box: 
     return p, x0, goal
 
 
+# differential drive (Section V model): turn rate within +-pi rad/s, tangential
+# acceleration within +-1 m/s^2, speed within +-1 m/s (the unicycle's speed bound)
+DIFFDRIVE_LIMITS = dict(u_lo=(-math.pi, -1.0, 0.0), u_hi=(math.pi, 1.0, 0.0), v_max=1.0)
+
+
+def diffdrive_circle(n: int = 8, horizon: int = 100, n_samples: int = 2048, radius: float = 2.0,
+                     **kw) -> Tuple[Problem, np.ndarray, np.ndarray]:
+    """Differential-drive antipodal circle swap (Section V-A scenario with the
+    paper's own differential-drive model)."""
+    s, g = circle_swap(n, radius)
+    lim = DIFFDRIVE_LIMITS.copy()
+    lim.update(kw)
+    p = Problem(dyn=DIFFDRIVE, n_robots=n, horizon=horizon, n_samples=n_samples, **lim)
+    x0, goal = make_states(DIFFDRIVE, s, g)
+    return p, x0, goal
+
+
 def holo3d_sphere(n: int = 16, horizon: int = 100, n_samples: int = 8192, radius: float = 2.0,
                   **kw) -> Tuple[Problem, np.ndarray, np.ndarray]:
     """3D holonomic antipodal sphere swap (16 robots, T=100, M=8192)."""
@@ -170,6 +191,8 @@ def random_instance(rng: np.random.Generator, dyn: int, n: int, horizon: int, n_
     g = random_points(rng, n, dp, box, min_sep)
     if dyn == UNICYCLE:
         lim = dict(u_lo=(-1.0, -math.pi, 0.0), u_hi=(1.0, math.pi, 0.0), v_max=0.0)
+    elif dyn == DIFFDRIVE:
+        lim = DIFFDRIVE_LIMITS.copy()
     else:
         lim = dict(u_lo=(-1.0, -1.0, -1.0), u_hi=(1.0, 1.0, 1.0), v_max=2.0)
     lim.update(kw)

@@ -64,4 +64,8 @@ def problems_small():
     out.append(("holo3d_n1_T9_M33", p, x0, g))
     p, x0, g = W.random_instance(rng, W.UNICYCLE, 2, 1, 1, box=3.0)
     out.append(("unicycle_n2_T1_M1", p, x0, g))
+    p, x0, g = W.diffdrive_circle(n=6, horizon=33, n_samples=130, radius=1.5)
+    out.append(("diffdrive_n6_T33_M130", p, x0, g))
+    p, x0, g = W.random_instance(rng, W.DIFFDRIVE, 11, 24, 96, box=4.0, min_sep=0.7)
+    out.append(("diffdrive_n11_T24_M96", p, x0, g))
     return out

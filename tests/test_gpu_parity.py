@@ -369,7 +369,8 @@ def test_autotuned_tile_keeps_parity(L, tmp_path):
 
 
 @pytest.mark.parametrize("dyn,n,T,M,S,Tb", [(W.UNICYCLE, 8, 100, 2048, 8, 16), (W.HOLO3D, 5, 37, 77, 8, 8),
-                                           (W.HOLO2D, 3, 41, 50, 16, 6), (W.HOLO3D, 16, 20, 40, 4, 4)])
+                                           (W.HOLO2D, 3, 41, 50, 16, 6), (W.HOLO3D, 16, 20, 40, 4, 4),
+                                           (W.DIFFDRIVE, 6, 31, 90, 8, 8)])
 def test_cooperative_kernel_is_bit_identical(L, dyn, n, T, M, S, Tb):
     """Replica lanes sharing the draws and pair checks reproduce the one-lane
     kernel exactly: draws, rewards, hit counts and a whole iteration."""
@@ -422,7 +423,8 @@ def test_negative_rewards_in_partial_waves(L):
     assert np.array_equal(_np(u), expect)
 
 
-@pytest.mark.parametrize("dyn,n,T,M", [(W.HOLO3D, 7, 23, 301), (W.UNICYCLE, 12, 40, 256), (W.HOLO2D, 2, 9, 64)])
+@pytest.mark.parametrize("dyn,n,T,M", [(W.HOLO3D, 7, 23, 301), (W.UNICYCLE, 12, 40, 256), (W.HOLO2D, 2, 9, 64),
+                                       (W.DIFFDRIVE, 9, 28, 200)])
 def test_tile_does_not_change_results(L, dyn, n, T, M):
     """Samples per workgroup, time block and replica lanes change speed only:
     a whole iteration gives the same bits for every admissible tile."""
