@@ -50,6 +50,9 @@ enum {
     D4_SAFE_PAIRS = 2   /* r_safe = -(number of colliding partners) instead of -1 */
 };
 
+/* Most static obstacles of one problem. */
+#define D4_MAX_OBSTACLES 16
+
 /*
  * One planning problem and its sampler settings.  Problem data follow the
  * problem definition of Section III (team size, radius R_a, dynamics, horizon,
@@ -78,6 +81,12 @@ typedef struct d4_problem {
     uint32_t flags;         /* D4_NORMALIZE | D4_SAFE_PAIRS */
     uint32_t instance_id;   /* fourth Philox counter word */
     uint64_t seed;          /* Philox key */
+    /* Static circular (spherical in 3D) obstacles of the appendix: each state
+     * within R_a + radius + epsilon of any obstacle costs a binary penalty -1
+     * in the team reward, weighted like r_safe; success also requires every
+     * state farther than R_a + radius from every obstacle. */
+    int32_t n_obstacles;                      /* 0..D4_MAX_OBSTACLES */
+    float obstacles[D4_MAX_OBSTACLES][4];     /* centre x, y, z (z unused in 2D), radius >= 0 */
 } d4_problem;
 
 /* Outcome of one iteration, written by d4_denoise_iter (host memory). */
@@ -90,6 +99,7 @@ typedef struct d4_stats {
                                (feasibility holds by construction; Sec. V-A reads success as
                                feasible and conflict-free) */
     int32_t at_goal;        /* terminal condition: every robot within goal_tol of its goal at t = T */
+    int32_t obstacle_hits;  /* robot-steps within an obstacle's reward distance (t = 1..T) */
     int32_t status;         /* D4_OK or D4_ENONFINITE */
 } d4_stats;
 

@@ -21,6 +21,12 @@ Readings (the paper is ambiguous or silent):
 * at_goal: every robot within goal_tol of its goal at t = T (the terminal
   condition read with a tolerance), reported beside success.
 * objective (Eq. objective): fraction of robot-steps t = 1..T within goal_tol.
+* Obstacles (appendix, "a binary penalty term for whether the robot collides
+  with any obstacle" added to Eq. generic-reward): r_obs(k, t) = -1 when robot
+  k is within R_a + r_o + epsilon of some obstacle o, weighted like r_safe
+  (w_safe); the predicate is |p_k - c_o|^2 <= (R_a + r_o + epsilon)^2, formed
+  like the pair predicate.  Success also requires every state strictly
+  farther than R_a + r_o from every obstacle.
 
 Pinned by brute-force pair loops on small teams, a closed-form head-on pass,
 closed-form rewards of stationary teams and permutation invariance
@@ -48,6 +54,38 @@ def pair_dist_sq(pos, dtype):
     for c in range(1, p.shape[-1]):
         acc = acc + d[..., c] * d[..., c]
     return acc
+
+
+def _obstacles(prob, dp):
+    """(centres [O][d_p], radii [O]) of the problem's obstacles, FP32-rounded."""
+    obs = np.asarray(prob.obstacles, dtype=np.float32).reshape(-1, 4)
+    return obs[:, :dp].astype(np.float64), obs[:, 3].astype(np.float64)
+
+
+def obstacle_dist_sq(pos, centres, dtype):
+    """|p - c_o|^2 for every obstacle; pos [..., d_p] -> [..., O] in dtype,
+    in the pair predicate's order ((dx*dx + dy*dy) + dz*dz)."""
+    p = np.asarray(pos).astype(dtype)[..., None, :]
+    d = p - np.asarray(centres).astype(dtype)
+    acc = d[..., 0] * d[..., 0]
+    for c in range(1, d.shape[-1]):
+        acc = acc + d[..., c] * d[..., c]
+    return acc
+
+
+def obstacle_hits(prob, x, pred_dtype=np.float64):
+    """[M, n, T] bool: the state at t = 1..T is within R_a + r_o + epsilon of some obstacle."""
+    _, _, dp = dims(prob.dyn)
+    x = np.asarray(x)
+    M, n, T1, _ = x.shape
+    cen, rad = _obstacles(prob, dp)
+    if len(rad) == 0:
+        return np.zeros((M, n, T1 - 1), dtype=bool)
+    ra = float(np.float32(prob.robot_radius))
+    eps = float(np.float32(prob.safety_margin))
+    thr = (ra + rad + eps) ** 2
+    d2 = obstacle_dist_sq(x[:, :, 1:, :dp], cen, pred_dtype)          # [M, n, T, O]
+    return (d2 <= thr.astype(pred_dtype)).any(axis=-1)
 
 
 def reward(prob, x, goal, pred_dtype=np.float64):
@@ -80,8 +118,9 @@ def reward(prob, x, goal, pred_dtype=np.float64):
     else:
         r_safe = -(partners > 0).astype(np.float64)
     r_safe = np.moveaxis(r_safe, 1, 2)                                # [M, n, T]
+    r_obs = -obstacle_hits(prob, x, pred_dtype).astype(np.float64)   # [M, n, T]
     w = float(np.float32(prob.w_safe))
-    r = (r_goal + w * r_safe).sum(axis=(1, 2)) / (n * T)
+    r = (r_goal + w * (r_safe + r_obs)).sum(axis=(1, 2)) / (n * T)
     hits = np.triu(hit, k=1).sum(axis=(1, 2, 3)).astype(np.int64)
     robots_hit = (partners > 0).sum(axis=(1, 2)).astype(np.int64)
     return r, hits, robots_hit
@@ -96,7 +135,12 @@ def success(prob, x, goal):
     pt = np.moveaxis(pos, 2, 1)
     d = np.sqrt(pair_dist_sq(pt, np.float64))
     d = d + np.eye(n) * 1e30
-    return (d > 2.0 * float(np.float32(prob.robot_radius))).all(axis=(1, 2, 3))
+    safe = (d > 2.0 * float(np.float32(prob.robot_radius))).all(axis=(1, 2, 3))
+    cen, rad = _obstacles(prob, dp)
+    if len(rad):
+        do = np.sqrt(obstacle_dist_sq(pos, cen, np.float64))              # [M, n, T, O]
+        safe &= (do > float(np.float32(prob.robot_radius)) + rad).all(axis=(1, 2, 3))
+    return safe
 
 
 def at_goal(prob, x, goal):

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libd4.so")
 
 D4_OK, D4_EINVAL, D4_ENOMEM, D4_EHIP, D4_ENONFINITE, D4_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+MAX_OBSTACLES = 16
 
 
 class D4Error(RuntimeError):
@@ -34,12 +35,14 @@ class D4Problem(ctypes.Structure):
         ("w_safe", c_float), ("temperature", c_float), ("beta_min", c_float), ("beta_max", c_float),
         ("u_lo", c_float * 3), ("u_hi", c_float * 3), ("v_max", c_float), ("goal_tol", c_float),
         ("d0_floor", c_float), ("flags", c_uint32), ("instance_id", c_uint32), ("seed", c_uint64),
+        ("n_obstacles", c_int32), ("obstacles", (c_float * 4) * MAX_OBSTACLES),
     ]
 
 
 class D4Stats(ctypes.Structure):
     _fields_ = [("reward", c_float), ("objective", c_float), ("hits", c_int32),
-                ("robots_hit", c_int32), ("success", c_int32), ("at_goal", c_int32), ("status", c_int32)]
+                ("robots_hit", c_int32), ("success", c_int32), ("at_goal", c_int32), ("obstacle_hits", c_int32),
+                ("status", c_int32)]
 
 
 def _load():
@@ -93,6 +96,13 @@ def to_c(p: Problem) -> D4Problem:
     for i in range(3):
         c.u_lo[i] = float(p.u_lo[i])
         c.u_hi[i] = float(p.u_hi[i])
+    obs = list(p.obstacles)
+    if len(obs) > MAX_OBSTACLES:
+        raise ValueError(f"at most {MAX_OBSTACLES} obstacles")
+    c.n_obstacles = len(obs)
+    for i, o in enumerate(obs):
+        for j in range(4):
+            c.obstacles[i][j] = float(o[j])
     return c
 
 
@@ -230,7 +240,8 @@ class Context:
         torch.cuda.current_stream().synchronize()
         s = self._stats
         return dict(reward=s.reward, objective=s.objective, hits=s.hits, robots_hit=s.robots_hit,
-                    success=bool(s.success), at_goal=bool(s.at_goal), status=s.status)
+                    success=bool(s.success), at_goal=bool(s.at_goal), obstacle_hits=s.obstacle_hits,
+                    status=s.status)
 
 
 def plan(p: Problem, x0, goal, iterations: int, u_init=None, stop_on_success=False):
@@ -254,7 +265,8 @@ def plan(p: Problem, x0, goal, iterations: int, u_init=None, stop_on_success=Fal
 
 def _stats_dict(s):
     return dict(reward=s.reward, objective=s.objective, hits=s.hits, robots_hit=s.robots_hit,
-                success=bool(s.success), at_goal=bool(s.at_goal), status=s.status)
+                success=bool(s.success), at_goal=bool(s.at_goal), obstacle_hits=s.obstacle_hits,
+                status=s.status)
 
 
 class BatchContext:

@@ -45,7 +45,7 @@ int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStre
     if (FROM_X) tile.R = 1;
     const dim3 block(tile.R * tile.S * p->n_robots);
     const size_t lds = rollfit_lds(p, tile);
-    if (lds > 160 * 1024) return fail(D4_EUNSUPPORTED, "reward kernel needs %zu bytes of LDS", lds);
+    if (lds > LDS_DYNAMIC_MAX) return fail(D4_EUNSUPPORTED, "reward kernel needs %zu bytes of LDS", lds);
     if (tile.S * p->n_robots > 256 || tile.R * tile.S * p->n_robots > 1024)
         return fail(D4_EINVAL, "workgroup of %d x %d x %d lanes too large", tile.R, tile.S, p->n_robots);
     if (tile.R > 1) {
@@ -216,6 +216,13 @@ int enqueue_iteration(d4_ctx* c, hipStream_t st) {
     f.w_safe = p->w_safe;
     f.d0_floor = p->d0_floor;
     f.flags = p->flags;
+    f.n_obs = p->n_obstacles;
+    f.obs = nullptr;
+    f.obs_safe2 = nullptr;
+    for (int o = 0; o < p->n_obstacles; ++o) {
+        f.obs_inline[o] = obstacle_reward(p, o);
+        f.safe2_inline[o] = obstacle_safe2(p, o);
+    }
     switch (p->dyn) {
         case HOLO2D: hipLaunchKernelGGL(k_apply_final<HOLO2D>, dim3(1), dim3(256), 0, st, f); break;
         case HOLO3D: hipLaunchKernelGGL(k_apply_final<HOLO3D>, dim3(1), dim3(256), 0, st, f); break;
@@ -499,7 +506,7 @@ int tile_ok(const d4_problem* p, Tile t) {
     if (t.S < 1 || t.S > 64 || t.S * p->n_robots > 256) return fail(D4_EINVAL, "samples per group %d invalid", t.S);
     if (t.R < 1 || t.R > 8 || t.R * t.S * p->n_robots > 1024) return fail(D4_EINVAL, "replicas %d invalid", t.R);
     if (t.Tb < cs || t.Tb > 64 || t.Tb % cs) return fail(D4_EINVAL, "steps per block %d invalid", t.Tb);
-    if (rollfit_lds(p, t) > 160 * 1024) return fail(D4_EUNSUPPORTED, "tile needs too much LDS");
+    if (rollfit_lds(p, t) > LDS_DYNAMIC_MAX) return fail(D4_EUNSUPPORTED, "tile needs too much LDS");
     return D4_OK;
 }
 

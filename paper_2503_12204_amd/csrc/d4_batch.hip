@@ -183,6 +183,11 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
         }
         in.sc = step_consts(&p);
         in.inst_id = p.instance_id;
+        in.n_obs = p.n_obstacles;
+        for (int o = 0; o < p.n_obstacles; ++o) {
+            in.obs[o] = obstacle_reward(&p, o);
+            in.obs_safe2[o] = obstacle_safe2(&p, o);
+        }
         b->insts.push_back(in);
         const double cost = tile_cost(p);
         for (long long m0 = 0; m0 < M; m0 += t.S) tl.push_back({cost, BatchTile{j, (int)m0}});
@@ -196,7 +201,7 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
         orr += M;
         ot += (long long)p.n_robots * (p.horizon + 1) * s.dx;
     }
-    if (lds > 160 * 1024) {
+    if (lds > LDS_DYNAMIC_MAX) {
         delete b;
         return fail(D4_EUNSUPPORTED, "reward tiles need %zu bytes of LDS", lds);
     }

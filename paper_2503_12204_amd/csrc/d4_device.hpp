@@ -21,6 +21,7 @@
 namespace d4 {
 
 enum { HOLO2D = 0, HOLO3D = 1, UNICYCLE = 2, DIFFDRIVE = 3 };
+constexpr int MAX_OBS = 16;   // static obstacles per problem
 enum { FLAG_NORMALIZE = 1, FLAG_SAFE_PAIRS = 2 };
 
 // ------------------------------------------------------------------ Philox

@@ -46,6 +46,10 @@ inline int fail(int code, const char* fmt, ...) {
             return fail(D4_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
     } while (0)
 
+// LDS a reward kernel may request dynamically: 160 KiB per CU less room for
+// the kernels' static arrays (staged obstacles, reductions).
+constexpr size_t LDS_DYNAMIC_MAX = 160 * 1024 - 1024;
+
 struct Shape {
     int dx, du, dp;
 };
@@ -86,6 +90,13 @@ inline int validate(const d4_problem* p) {
         if (!(p->u_lo[d] <= p->u_hi[d]) || !finite_f(p->u_lo[d]) || !finite_f(p->u_hi[d]))
             return fail(D4_EINVAL, "control box %d is empty or non-finite", d);
     if (p->dyn != UNICYCLE && !(p->v_max >= 0.0f)) return fail(D4_EINVAL, "v_max must be >= 0");
+    if (p->n_obstacles < 0 || p->n_obstacles > D4_MAX_OBSTACLES)
+        return fail(D4_EINVAL, "n_obstacles %d outside 0..%d", p->n_obstacles, D4_MAX_OBSTACLES);
+    for (int o = 0; o < p->n_obstacles; ++o) {
+        for (int c = 0; c < 4; ++c)
+            if (!finite_f(p->obstacles[o][c])) return fail(D4_EINVAL, "obstacle %d is not finite", o);
+        if (!(p->obstacles[o][3] >= 0.0f)) return fail(D4_EINVAL, "obstacle %d has a negative radius", o);
+    }
     const double D = (double)p->n_robots * p->horizon * s.du;
     if (D * p->n_samples > 4.0e9) return fail(D4_EUNSUPPORTED, "D*M = %.0f too large", D * p->n_samples);
     if ((D + 3) / 4 > 65535.0) return fail(D4_EUNSUPPORTED, "D = %.0f too large for one launch", D);
@@ -132,6 +143,18 @@ inline Schedule make_schedule(const d4_problem* p) {
 inline float thr2_reward(const d4_problem* p) {
     const double thr = 2.0 * (double)p->robot_radius + (double)p->safety_margin;
     return (float)(thr * thr);
+}
+
+// Obstacle o as (centre, (R_a + r_o + epsilon)^2) for the reward, and its
+// squared safety distance (R_a + r_o)^2 for success; squares formed in FP64
+// from the FP32 parameters, then rounded.
+inline float4 obstacle_reward(const d4_problem* p, int o) {
+    const double thr = (double)p->robot_radius + (double)p->obstacles[o][3] + (double)p->safety_margin;
+    return make_float4(p->obstacles[o][0], p->obstacles[o][1], p->obstacles[o][2], (float)(thr * thr));
+}
+inline float obstacle_safe2(const d4_problem* p, int o) {
+    const double s = (double)p->robot_radius + (double)p->obstacles[o][3];
+    return (float)(s * s);
 }
 
 inline StepConsts step_consts(const d4_problem* p) {
@@ -226,13 +249,13 @@ inline size_t rollfit_lds(const d4_problem* p, Tile t) {
     if (t.R > 1) {  // cooperative kernel: draws, single-buffered positions, masks
         const size_t G = (size_t)t.Tb * s.du / 4 + 1;
         const size_t a = n * G * 4 * t.S * 4 + (size_t)t.Tb * n2 * t.S * slot + (size_t)2 * t.Tb * t.S * 4;
-        const size_t b = (size_t)(2 + t.R) * n * t.S * 4;
+        const size_t b = (size_t)(3 + t.R) * n * t.S * 4;
         return a > b ? a : b;
     }
     // one-lane kernel: positions [Tb][2n-1][S], boxes [n][S][2], masks [2][Tb][S], flags [2][S]
     const size_t a = (size_t)t.Tb * n2 * t.S * slot + (size_t)2 * n * t.S * slot +
                      (size_t)2 * t.Tb * t.S * 4 + (size_t)2 * t.S * 4;
-    const size_t b = (size_t)3 * n * t.S * 4;
+    const size_t b = (size_t)4 * n * t.S * 4;
     return a > b ? a : b;
 }
 
@@ -270,6 +293,9 @@ inline RollFitArgs base_args(const d4_problem* p, Tile tile) {
     a.key1 = (uint32_t)(p->seed >> 32);
     a.inst = p->instance_id;
     a.flags = p->flags;
+    a.n_obs = p->n_obstacles;
+    a.obs = nullptr;
+    for (int o = 0; o < p->n_obstacles; ++o) a.obs_inline[o] = obstacle_reward(p, o);
     return a;
 }
 

@@ -59,7 +59,32 @@ struct RollFitArgs {
     StepConsts sc;
     uint32_t key0, key1, step, iter, inst;
     uint32_t flags;
+    // static obstacles (appendix): centre and squared reward distance
+    // (R_a + r_o + epsilon)^2 each, from device memory (obs) or, when obs is
+    // null, from the kernel arguments themselves
+    int n_obs;
+    const float4* obs;
+    float4 obs_inline[MAX_OBS];
 };
+
+// Stage a problem's obstacles in LDS (static, MAX_OBS slots); the caller
+// synchronises the workgroup before the first use.
+__device__ __forceinline__ void stage_obstacles(const RollFitArgs& a, float4* obs_l) {
+    const int tid = threadIdx.x;
+    if (tid < a.n_obs) obs_l[tid] = a.obs ? a.obs[tid] : a.obs_inline[tid];
+}
+
+// Binary obstacle hit of a position: within the reward distance of any obstacle.
+template <int DP>
+__device__ __forceinline__ int obstacle_hit(const float* x, const float4* obs_l, int n_obs) {
+    int hit = 0;
+    for (int o = 0; o < n_obs; ++o) {
+        const float4 c = obs_l[o];
+        const float cc[3] = {c.x, c.y, c.z};
+        hit |= pair_d2<DP>(x, cc) <= c.w ? 1 : 0;
+    }
+    return hit;
+}
 
 // Position slot of one robot in LDS: float2 in the plane, float4 (w unused) in space.
 template <int DP>
@@ -195,7 +220,11 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     const float inv_d0 = inv_start_dist(goal_d2<DP>(x, g), a.d0_floor);
 
     float goal_acc = 0.0f;
-    int safe_cnt = 0, hit_cnt = 0;
+    int safe_cnt = 0, hit_cnt = 0, obs_cnt = 0;
+    __shared__ float4 obs_l[MAX_OBS];
+    stage_obstacles(a, obs_l);
+    __syncthreads();
+    const int n_obs = a.n_obs;
 
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
     const uint32_t c2 = (iter << 16) | a.step;
@@ -226,6 +255,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     // goal term, LDS position and bounding box of the state after step tt of the block
     auto after_step = [&](int tt) {
         goal_acc += goal_term(fast_sqrt(goal_d2<DP>(x, g)), inv_d0);
+        if (n_obs) obs_cnt += obstacle_hit<DP>(x, obs_l, n_obs);
 #pragma unroll
         for (int c = 0; c < DP; ++c) {
             blo[c] = fminf(blo[c], x[c]);
@@ -380,21 +410,24 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     float* rg = lds;
     int* rs = reinterpret_cast<int*>(lds + n * S);
     int* rh = rs + n * S;
+    int* ro = rh + n * S;
     if (active) {
         rg[k * S + ms] = goal_acc;
         rs[k * S + ms] = safe_cnt;
         rh[k * S + ms] = hit_cnt;
+        ro[k * S + ms] = obs_cnt;
     }
     __syncthreads();
     if (k_raw == 0 && live) {
         float gs = 0.0f;
-        int ss = 0, hs = 0;
+        int ss = 0, hs = 0, os = 0;
         for (int kk = 0; kk < n; ++kk) {
             gs += rg[kk * S + ms];
             ss += rs[kk * S + ms];
             hs += rh[kk * S + ms];
+            os += ro[kk * S + ms];
         }
-        const float pen = pairs_mode ? (float)(2 * hs) : (float)ss;
+        const float pen = (float)((pairs_mode ? 2 * hs : ss) + os);
         const float rv = team_reward(gs, a.w_safe, pen, n * T);
         a.r[m] = rv;
         a.hits[m] = hs;
@@ -449,7 +482,11 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
     for (int c = 0; c < DP; ++c) g[c] = a.goal[k * DP + c];
     const float inv_d0 = inv_start_dist(goal_d2<DP>(x, g), a.d0_floor);
     float goal_acc = 0.0f;
-    int safe_cnt = 0, hit_cnt = 0;
+    int safe_cnt = 0, hit_cnt = 0, obs_cnt = 0;
+    __shared__ float4 obs_l[MAX_OBS];
+    stage_obstacles(a, obs_l);
+    __syncthreads();
+    const int n_obs = a.n_obs;
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
     const uint32_t c2 = (iter << 16) | a.step;
     const uint32_t ebase = (uint32_t)(k * T * DU);
@@ -503,6 +540,7 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
                 }
                 DY::step(x, aux, u, a.sc);
                 goal_acc += goal_term(fast_sqrt(goal_d2<DP>(x, g)), inv_d0);
+                if (n_obs) obs_cnt += obstacle_hit<DP>(x, obs_l, n_obs);
                 const PT v = PS::pack(x);
                 PT* slot = pos + (tt * n2 + k) * S + ms;
                 slot[0] = v;
@@ -528,23 +566,26 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
     float* rg = lds;
     int* rs = reinterpret_cast<int*>(lds + group);
     int* rh = rs + group;                  // [R][n][S]
+    int* ro = rh + R * group;              // [n][S]
     if (active) {
         rh[rep * group + k * S + ms] = hit_cnt;
         if (rep == 0) {
             rg[k * S + ms] = goal_acc;
             rs[k * S + ms] = safe_cnt;
+            ro[k * S + ms] = obs_cnt;
         }
     }
     __syncthreads();
     if (rep == 0 && k == 0 && live) {
         float gs = 0.0f;
-        int ss = 0, hs = 0;
+        int ss = 0, hs = 0, os = 0;
         for (int kk = 0; kk < n; ++kk) {
             gs += rg[kk * S + ms];
             ss += rs[kk * S + ms];
+            os += ro[kk * S + ms];
             for (int rr = 0; rr < R; ++rr) hs += rh[rr * group + kk * S + ms];
         }
-        const float pen = pairs_mode ? (float)(2 * hs) : (float)ss;
+        const float pen = (float)((pairs_mode ? 2 * hs : ss) + os);
         const float rv = team_reward(gs, a.w_safe, pen, n * T);
         a.r[m] = rv;
         a.hits[m] = hs;
@@ -881,13 +922,21 @@ struct FinalArgs {
     const float* x0;      // [n][dx]
     const float* goal;    // [n][dp]
     float* traj;          // [n][T+1][dx]
-    float* stats;         // d4_stats layout: reward, objective, hits, robots_hit, success, at_goal, status
+    float* stats;         // d4_stats layout: reward, objective, hits, robots_hit, success, at_goal,
+                          // obstacle_hits, status
     const int* status;    // sticky status of the iteration
     int n, T;
     float ulo[3], uhi[3];
     StepConsts sc;
     float thr2, safe2, goal_tol, w_safe, d0_floor;
     uint32_t flags;
+    // obstacles: (centre, reward distance^2) and safety distance^2, from device
+    // memory (obs, obs_safe2) or, when obs is null, from the arguments
+    int n_obs;
+    const float4* obs;
+    const float* obs_safe2;
+    float4 obs_inline[MAX_OBS];
+    float safe2_inline[MAX_OBS];
 };
 
 // One block: apply the deformation, roll the plan out, score it.
@@ -896,7 +945,7 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
     using DY = Dyn<DYN>;
     constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
     __shared__ float red_g[256];
-    __shared__ int red_s[256], red_h[256], red_o[256], red_bad[256];
+    __shared__ int red_s[256], red_h[256], red_o[256], red_bad[256], red_ob[256];
     const int n = a.n, T = a.T, D = n * T * DU;
     const int tid = threadIdx.x;
     for (int e = tid; e < D; e += blockDim.x) {
@@ -905,7 +954,9 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
     }
     __syncthreads();
     float gacc = 0.0f;
-    int at_goal = 0, term_bad = 0;
+    int at_goal = 0, term_bad = 0, obs_cnt = 0, obs_unsafe = 0;
+    const float4* ob = a.obs ? a.obs : a.obs_inline;
+    const float* ob_safe2 = a.obs ? a.obs_safe2 : a.safe2_inline;
     if (tid < n) {
         const int k = tid;
         float x[DX], aux[DY::AUX], g[DP];
@@ -929,6 +980,15 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
             gacc += goal_term(dist, inv_d0);
             at_goal += dist <= a.goal_tol;
             if (t == T - 1) term_bad = dist > a.goal_tol;
+            int hit = 0;
+            for (int o = 0; o < a.n_obs; ++o) {
+                const float4 c = ob[o];
+                const float cc[3] = {c.x, c.y, c.z};
+                const float d2 = pair_d2<DP>(x, cc);
+                hit |= d2 <= c.w ? 1 : 0;
+                obs_unsafe |= d2 <= ob_safe2[o] ? 1 : 0;
+            }
+            obs_cnt += hit;
         }
     }
     __syncthreads();
@@ -958,19 +1018,21 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
     red_s[tid] = safe_cnt;
     red_h[tid] = hit_cnt;
     red_o[tid] = at_goal;
-    red_bad[tid] = unsafe | (term_bad << 1);
+    red_bad[tid] = (unsafe | obs_unsafe) | (term_bad << 1);
+    red_ob[tid] = obs_cnt;
     __syncthreads();
     if (tid == 0) {
         float gs = 0.0f;
-        int ss = 0, hs = 0, os = 0, bad = 0;
+        int ss = 0, hs = 0, os = 0, bad = 0, obt = 0;
         for (int i = 0; i < (int)blockDim.x; ++i) {
             gs += red_g[i];
             ss += red_s[i];
             hs += red_h[i];
             os += red_o[i];
             bad |= red_bad[i];
+            obt += red_ob[i];
         }
-        const float pen = (a.flags & FLAG_SAFE_PAIRS) ? (float)(2 * hs) : (float)ss;
+        const float pen = (float)(((a.flags & FLAG_SAFE_PAIRS) ? 2 * hs : ss) + obt);
         a.stats[0] = team_reward(gs, a.w_safe, pen, n * T);
         a.stats[1] = (float)os / (float)(n * T);
         int* si = reinterpret_cast<int*>(a.stats);
@@ -978,7 +1040,8 @@ __device__ __forceinline__ void apply_final_body(const FinalArgs& a) {
         si[3] = ss;
         si[4] = (bad & 1) ? 0 : 1;
         si[5] = (bad & 2) ? 0 : 1;
-        si[6] = a.status ? *a.status : 0;
+        si[6] = obt;
+        si[7] = a.status ? *a.status : 0;
     }
 }
 
@@ -993,7 +1056,9 @@ __global__ void __launch_bounds__(256) k_apply_final(const FinalArgs a) {
 // team size, horizon, dynamics and limits are its own.  Offsets count floats
 // (or samples) into packed arrays in instance order.
 struct BatchInst {
-    int n, T, dyn, S, Tb, mode, D;
+    int n, T, dyn, S, Tb, mode, D, n_obs;
+    float4 obs[MAX_OBS];        // centre, reward distance^2
+    float obs_safe2[MAX_OBS];   // safety distance^2
     long long x0, goal, u, eps, r, traj;
     float thr2, safe2, w_safe, d0_floor, goal_tol;
     float ulo[3], uhi[3];
@@ -1060,6 +1125,8 @@ static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArg
     a.iter = 0;
     a.inst = in.inst_id;
     a.flags = b.flags;
+    a.n_obs = in.n_obs;
+    a.obs = in.obs;
     const bool al = in.mode == MODE_FUSED_ALIGNED;
     switch (in.dyn) {
         case HOLO2D:
@@ -1129,7 +1196,7 @@ struct BatchFinalArgs {
     const float* x0;
     const float* goal;
     float* traj;
-    float* stats;        // [count][7], d4_stats layout
+    float* stats;        // [count][8], d4_stats layout
     const int* status;   // [count]
     uint32_t flags;
 };
@@ -1143,7 +1210,7 @@ static __global__ void __launch_bounds__(256) k_batch_final(const BatchFinalArgs
     a.x0 = b.x0 + in.x0;
     a.goal = b.goal + in.goal;
     a.traj = b.traj + in.traj;
-    a.stats = b.stats + 7 * (size_t)blockIdx.x;
+    a.stats = b.stats + 8 * (size_t)blockIdx.x;
     a.status = b.status + blockIdx.x;
     a.n = in.n;
     a.T = in.T;
@@ -1158,6 +1225,9 @@ static __global__ void __launch_bounds__(256) k_batch_final(const BatchFinalArgs
     a.w_safe = in.w_safe;
     a.d0_floor = in.d0_floor;
     a.flags = b.flags;
+    a.n_obs = in.n_obs;
+    a.obs = in.obs;
+    a.obs_safe2 = in.obs_safe2;
     switch (in.dyn) {
         case HOLO2D: apply_final_body<HOLO2D>(a); break;
         case HOLO3D: apply_final_body<HOLO3D>(a); break;

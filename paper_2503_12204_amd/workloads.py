@@ -63,6 +63,8 @@ class Problem:
     flags: int = FLAG_NORMALIZE
     instance_id: int = 0
     seed: int = 0
+    # static obstacles (appendix): (x, y, z, radius) each, z unused in 2D
+    obstacles: Tuple[Tuple[float, float, float, float], ...] = ()
 
     @property
     def dx(self) -> int:
@@ -169,6 +171,29 @@ def diffdrive_circle(n: int = 8, horizon: int = 100, n_samples: int = 2048, radi
     lim.update(kw)
     p = Problem(dyn=DIFFDRIVE, n_robots=n, horizon=horizon, n_samples=n_samples, **lim)
     x0, goal = make_states(DIFFDRIVE, s, g)
+    return p, x0, goal
+
+
+def circle_obstacles(n_obs: int, ring: float = 0.8, big: float = 0.6,
+                     small: float = 0.3) -> Tuple[Tuple[float, float, float, float], ...]:
+    """Obstacles for the antipodal swap with obstacles (appendix): one large
+    disc at the centre, or n_obs small discs evenly on a ring around it."""
+    if n_obs <= 0:
+        return ()
+    if n_obs == 1:
+        return ((0.0, 0.0, 0.0, big),)
+    ang = 2.0 * np.pi * np.arange(n_obs) / n_obs + 0.25
+    return tuple((float(ring * np.cos(a)), float(ring * np.sin(a)), 0.0, small) for a in ang)
+
+
+def holo2d_circle_obstacles(n: int = 16, n_obs: int = 4, horizon: int = 100, n_samples: int = 2048,
+                            radius: float = 2.0, **kw) -> Tuple[Problem, np.ndarray, np.ndarray]:
+    """2D holonomic antipodal circle swap around static obstacles (appendix scenario)."""
+    s, g = circle_swap(n, radius)
+    p = Problem(dyn=HOLO2D, n_robots=n, horizon=horizon, n_samples=n_samples,
+                u_lo=(-1.0, -1.0, -1.0), u_hi=(1.0, 1.0, 1.0), v_max=2.0,
+                obstacles=circle_obstacles(n_obs), **kw)
+    x0, goal = make_states(HOLO2D, s, g)
     return p, x0, goal
 
 

@@ -32,6 +32,19 @@ def ambiguous_samples(prob, x, band=GUARD_BAND):
     return near.any(axis=(1, 2, 3))
 
 
+def ambiguous_obstacle_samples(prob, x, band=GUARD_BAND):
+    """Samples with a state inside the guard band of an obstacle's reward distance."""
+    dp = W.dims(prob.dyn)[2]
+    obs = np.asarray(prob.obstacles, dtype=np.float32).reshape(-1, 4).astype(np.float64)
+    M = np.asarray(x).shape[0]
+    if len(obs) == 0:
+        return np.zeros(M, dtype=bool)
+    pos = np.asarray(x, dtype=np.float64)[:, :, 1:, :dp]
+    d2 = ((pos[..., None, :] - obs[:, :dp]) ** 2).sum(-1)                    # [M, n, T, O]
+    thr = float(np.float32(prob.robot_radius)) + obs[:, 3] + float(np.float32(prob.safety_margin))
+    return (np.abs(d2 - thr * thr) <= band * thr * thr).any(axis=(1, 2, 3))
+
+
 def ambiguous_band_pairs(prob, x, band=GUARD_BAND):
     """Per sample, the number of (pair, step) checks inside the guard band."""
     dp = W.dims(prob.dyn)[2]
@@ -68,4 +81,9 @@ def problems_small():
     out.append(("diffdrive_n6_T33_M130", p, x0, g))
     p, x0, g = W.random_instance(rng, W.DIFFDRIVE, 11, 24, 96, box=4.0, min_sep=0.7)
     out.append(("diffdrive_n11_T24_M96", p, x0, g))
+    p, x0, g = W.holo2d_circle_obstacles(n=8, n_obs=3, horizon=40, n_samples=200)
+    out.append(("holo2d_obs3_n8_T40_M200", p, x0, g))
+    p, x0, g = W.random_instance(rng, W.HOLO3D, 6, 30, 90, box=3.0, min_sep=0.7,
+                                 obstacles=((1.5, 1.5, 1.5, 0.5), (0.5, 2.5, 1.0, 0.3)))
+    out.append(("holo3d_obs2_n6_T30_M90", p, x0, g))
     return out

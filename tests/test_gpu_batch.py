@@ -27,6 +27,11 @@ def test_batch_equals_single_problem_runs(L):
     inst = _mix(7, 160, 12, seed=3)
     inst.append(W.holo3d_sphere(n=32, horizon=20, n_samples=160))
     inst[-1] = (inst[-1][0].replace(n_steps=12, instance_id=7), inst[-1][1], inst[-1][2])
+    # obstacles are per instance (appendix penalty); the paper's differential drive too
+    q, x0q, gq = W.holo2d_circle_obstacles(n=6, n_obs=2, horizon=20, n_samples=160)
+    inst.append((q.replace(n_steps=12, instance_id=8), x0q, gq))
+    q, x0q, gq = W.diffdrive_circle(n=5, horizon=22, n_samples=160)
+    inst.append((q.replace(n_steps=12, instance_id=9), x0q, gq))
     probs = [p for p, _, _ in inst]
     print("shapes", [(p.dyn, p.n_robots, p.horizon) for p in probs], flush=True)
     bc = L.BatchContext(probs, [x for _, x, _ in inst], [g for _, _, g in inst])

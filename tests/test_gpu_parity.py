@@ -12,7 +12,7 @@ import pytest
 import torch
 
 from helpers import (FINAL_RTOL, REWARD_ATOL, STEP_ATOL, STEP_RTOL, ambiguous_band_pairs,
-                     ambiguous_samples, problems_small)
+                     ambiguous_obstacle_samples, ambiguous_samples, problems_small)
 from oracle import dynamics as odyn
 from oracle import fitness as ofit
 from oracle import mbd as ombd
@@ -148,7 +148,7 @@ def test_fused_step_parity(L, name, p, x0, g):
 def _check_rewards(p, ora, rg, hg, min_clear=0.25):
     """Hits must match exactly wherever no pair is inside the guard band; the
     rest may differ by the pairs inside the band.  Rewards follow the same split."""
-    amb = ambiguous_samples(p, ora["x"])
+    amb = ambiguous_samples(p, ora["x"]) | ambiguous_obstacle_samples(p, ora["x"])
     ok = ~amb
     assert ok.mean() >= min_clear, f"only {ok.sum()} of {ok.size} samples clear of the guard band"
     assert np.all(np.abs(rg[ok] - ora["r"][ok]) <= REWARD_ATOL), np.abs(rg[ok] - ora["r"][ok]).max()
@@ -452,3 +452,39 @@ def test_tile_does_not_change_results(L, dyn, n, T, M):
     for S, Tb, R, u, rew in plans[1:]:
         assert np.array_equal(u, plans[0][3]), f"tile {(S, Tb, R)}"
         assert rew == plans[0][4]
+
+
+@pytest.mark.parametrize("n_obs", [1, 4])
+def test_final_stats_with_obstacles(L, n_obs):
+    """The iteration's final scoring with obstacles (appendix penalty): on the
+    GPU's own FP32 trajectory the oracle's FP32 predicates give the same pair
+    hits, obstacle hits and success, and the same reward within FP32 sums."""
+    p, x0, g = W.holo2d_circle_obstacles(n=8, n_obs=n_obs, horizon=40, n_samples=256)
+    p = p.replace(n_steps=20)
+    ctx = L.Context(p)
+    u = torch.zeros((p.n_robots, p.horizon, p.du), dtype=torch.float32, device="cuda")
+    traj = torch.empty((p.n_robots, p.horizon + 1, p.dx), dtype=torch.float32, device="cuda")
+    for it in range(2):
+        st = ctx.denoise_iter(_cu(x0), _cu(g), u, it, traj=traj)
+    ctx.close()
+    x = _np(traj)[None]
+    r, hits, _ = ofit.reward(p, x, g, pred_dtype=np.float32)
+    assert st["hits"] == int(hits[0])
+    assert st["obstacle_hits"] == int(ofit.obstacle_hits(p, x, pred_dtype=np.float32).sum())
+    assert abs(st["reward"] - r[0]) <= 1e-5
+    assert st["success"] == bool(ofit.success(p, x.astype(np.float64), g)[0])
+    assert st["at_goal"] == bool(ofit.at_goal(p, x.astype(np.float64), g)[0])
+
+
+def test_obstacles_are_avoided(L):
+    """A robot crossing the centre plans around a large central obstacle:
+    without the penalty the straight line runs through it."""
+    p, x0, g = W.holo2d_circle_obstacles(n=2, n_obs=1, horizon=60, n_samples=1024)
+    plain = p.replace(obstacles=())
+    out = {}
+    for name, q in (("with", p), ("without", plain)):
+        u, hist = L.plan(q, x0, g, iterations=3)
+        x = _np(L.rollout(p, _cu(x0), u[None].contiguous()))
+        out[name] = int(ofit.obstacle_hits(p, x, pred_dtype=np.float32).sum())
+    assert out["without"] > 0
+    assert out["with"] == 0

@@ -149,3 +149,67 @@ def test_success_and_objective():
     assert list(fitness.at_goal(p, x, goal)) == [True, True, False]
     o = fitness.objective(p, x, goal)
     assert abs(o[0] - 2 / 8) < 1e-15 and abs(o[2] - 1 / 8) < 1e-15
+
+
+def test_obstacle_penalty_closed_forms():
+    """A robot passing a disc obstacle at constant speed along the x axis,
+    offset h from its centre: it is within R_a + r_o + epsilon at exactly the
+    steps with x_t^2 + h^2 <= thr^2, each costing w_safe / (nT); an
+    obstacle-free problem scores as before; obstacle order does not matter;
+    success needs every state strictly beyond R_a + r_o."""
+    T, v, h, r_o = 40, 0.1, 0.5, 0.4
+    p = W.Problem(dyn=W.HOLO2D, n_robots=1, horizon=T, w_safe=2.0,
+                  obstacles=((0.0, h, 0.0, r_o), (50.0, 50.0, 0.0, 1.0)))
+    x = np.zeros((1, 1, T + 1, 4))
+    x[0, 0, :, 0] = -2.0 + v * np.arange(T + 1)
+    goal = np.array([[2.0, 0.0]])
+    thr = 0.3 + r_o + 0.1
+    inside = (x[0, 0, 1:, 0] ** 2 + h * h) <= thr * thr
+    want = int(inside.sum())
+    assert want == 2 * int(np.floor(np.sqrt(thr * thr - h * h) / v)) + 1   # symmetric around x = 0
+    hit = fitness.obstacle_hits(p, x)
+    assert int(hit.sum()) == want
+    r, _, _ = fitness.reward(p, x, goal)
+    r_free, _, _ = fitness.reward(p.replace(obstacles=()), x, goal)
+    assert abs(r[0] - (r_free[0] - 2.0 * want / T)) < 1e-12
+    p_rev = p.replace(obstacles=tuple(reversed(p.obstacles)))
+    assert np.array_equal(fitness.reward(p_rev, x, goal)[0], r)
+    # success: the closest approach, h = 0.5 from the centre, is within R_a + r_o = 0.7: unsafe
+    assert not fitness.success(p, x, goal)[0]
+    assert fitness.success(p.replace(obstacles=((0.0, h + 0.8, 0.0, r_o),)), x, goal)[0]
+    # strictness: a state exactly R_a + r_o from the centre is unsafe
+    # (radii are the problem's FP32 values)
+    edge = float(np.float32(0.3)) + 0.25
+    x2 = np.zeros((1, 1, 2, 4))
+    x2[0, 0, :, 0] = edge
+    p2 = W.Problem(dyn=W.HOLO2D, n_robots=1, horizon=1, obstacles=((0.0, 0.0, 0.0, 0.25),))
+    assert not fitness.success(p2, x2, np.zeros((1, 2)))[0]
+    x2[0, 0, :, 0] = np.nextafter(edge, 1.0)
+    assert fitness.success(p2, x2, np.zeros((1, 2)))[0]
+
+
+def test_obstacle_predicate_fp32_matches_brute_force():
+    """The FP32 obstacle predicate equals a brute-force loop with the same
+    operation order, including states placed on the threshold."""
+    rng = np.random.default_rng(9)
+    obs = tuple((float(a), float(b), float(c), float(rr)) for a, b, c, rr in
+                zip(rng.uniform(-2, 2, 4), rng.uniform(-2, 2, 4), rng.uniform(-2, 2, 4), rng.uniform(0.1, 0.6, 4)))
+    p = W.Problem(dyn=W.HOLO3D, n_robots=3, horizon=6, obstacles=obs)
+    x = rng.uniform(-2.5, 2.5, size=(5, 3, 7, 6)).astype(np.float32)
+    # put one state exactly on an obstacle's FP32 threshold along x
+    thr = np.float32((float(np.float32(0.3)) + float(np.float32(obs[0][3])) + float(np.float32(0.1))) ** 2)
+    x[0, 0, 3, :3] = np.float32(obs[0][0]) + np.sqrt(thr), np.float32(obs[0][1]), np.float32(obs[0][2])
+    got = fitness.obstacle_hits(p, x, pred_dtype=np.float32)
+    for m in range(5):
+        for k in range(3):
+            for t in range(6):
+                any_hit = False
+                for o in obs:
+                    c = np.float32(o[:3])
+                    d = x[m, k, t + 1, :3] - c
+                    acc = np.float32(d[0] * d[0])
+                    acc = np.float32(acc + np.float32(d[1] * d[1]))
+                    acc = np.float32(acc + np.float32(d[2] * d[2]))
+                    t2 = np.float32((float(np.float32(0.3)) + float(np.float32(o[3])) + float(np.float32(0.1))) ** 2)
+                    any_hit |= bool(acc <= t2)
+                assert got[m, k, t] == any_hit
