@@ -222,8 +222,11 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     float goal_acc = 0.0f;
     int safe_cnt = 0, hit_cnt = 0, obs_cnt = 0;
     __shared__ float4 obs_l[MAX_OBS];
-    stage_obstacles(a, obs_l);
-    __syncthreads();
+    // the obstacle count is uniform over the grid, so the barrier is too
+    if (a.n_obs > 0) {
+        stage_obstacles(a, obs_l);
+        __syncthreads();
+    }
     const int n_obs = a.n_obs;
 
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
@@ -484,8 +487,11 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
     float goal_acc = 0.0f;
     int safe_cnt = 0, hit_cnt = 0, obs_cnt = 0;
     __shared__ float4 obs_l[MAX_OBS];
-    stage_obstacles(a, obs_l);
-    __syncthreads();
+    // the obstacle count is uniform over the grid, so the barrier is too
+    if (a.n_obs > 0) {
+        stage_obstacles(a, obs_l);
+        __syncthreads();
+    }
     const int n_obs = a.n_obs;
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
     const uint32_t c2 = (iter << 16) | a.step;
