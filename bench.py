@@ -28,39 +28,61 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-VALU_PEAK = 256 * 4 * 16 * 2.4e9      # lane-operations per second
+# gfx950 VALU issue rates (256 CUs x 4 SIMDs at 2.4 GHz), lanes per second:
+# a fused multiply-add issues a wave64 in 2 cycles (the 157.3 TFLOP/s FP32
+# vector figure: 32 FMA lanes per SIMD and cycle); other VALU instructions
+# (add, multiply, min/max, compares, selects, integer and logic, conversions,
+# the 32x32->64 product) in 4; transcendentals (reciprocal, square root) in 8.
+SIMD_HZ = 256 * 4 * 2.4e9
+FMA_RATE = SIMD_HZ * 32
+OTHER_RATE = SIMD_HZ * 16
+TRANS_RATE = SIMD_HZ * 8
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic VALU operations per robot*step*sample of the fused kernel: the
 # operations each step of the method needs in its leanest gfx950 form (one
 # VALU instruction per arithmetic step, a fused multiply-add or a 32x32->64
-# product counted once), independent of how the kernel schedules them.
+# product counted once), independent of how the kernel schedules them, split
+# into (fma, other, transcendental):
 #  - standard normal: Philox4x32-10 = 10 rounds of two 32x32->64 products and
-#    the XORs with the other words and the round key, plus the counter set-up:
-#    50 per block of 4 normals (12.5);
-#    Box-Muller per pair: uniform 3, ln 25 (division 8), -2 ln and the
-#    corrected square root 7, sin/cos with the quadrant rotation 27, two
-#    products 2 = 64 per pair (32); 44.5 per normal in all
-#  - sampled control: fma, fma, max, min = 4 per component
-#  - dynamics per step: double integrator 5 per axis; unicycle 13 (two heading
-#    updates, two hardware sin/cos pairs, Simpson sums); differential drive 17
-#    (the unicycle's plus the speed's two fused steps and its clip)
-#  - goal term: 2 d_p + 3 (squared distance, square root, fused step, sum)
-#  - bounding box of the block: 2 d_p
-#  - broad phase: (n - 1)/2 partners per robot and block of Tb steps, 4 d_p + 2
-#    each (two differences and a max per axis, squares and sums, compare, or)
-#  - collision flags: 3
+#    two three-input XORs, plus the counter set-up: 50 other per block of 4
+#    normals; Box-Muller per pair: uniform 3 other; ln 12 fma + 12 other +
+#    1 reciprocal (of which the division 6 fma + 1 other + 1 reciprocal);
+#    -2 ln 1 other; corrected square root 2 fma + 4 other + 1 square root;
+#    sin/cos with the quadrant rotation 8 fma + 19 other; two products 2 other.
+#    Per normal: 11 fma + 33 other + 1 transcendental.
+#  - sampled control: fma, fma, max, min per component
+#  - dynamics per step: double integrator 3 fma + 2 other (clip) per axis;
+#    unicycle 6 fma + 3 other + 4 transcendental (two heading updates, the
+#    mid-step and end-of-step sin/cos, Simpson sums); differential drive
+#    8 fma + 5 other + 4 transcendental (the speed's two steps and its clip)
+#  - goal term: squared distance d_p fma-or-product steps, square root, fused
+#    step, sum: d_p fma + (d_p + 2) other + 1 transcendental
+#  - bounding box of the block: 2 d_p other
+#  - broad phase: (n - 1)/2 partners per robot and block of Tb steps, d_p fma
+#    + (3 d_p + 2) other each (differences, max, squares and sums, compare, or)
+#  - collision flags: 3 other
 # The exact pair checks of partners the broad phase keeps are data dependent
-# and not counted (under 1% of pairs on the benchmark workloads).
-OPS_PER_NORMAL = 44.5
+# and not counted.
+NORMAL_OPS = (11.0, 33.0, 1.0)
 
 
 def ops_per_unit(dyn, n, steps_per_block):
+    """Algorithmic (fma, other, transcendental) VALU operations per robot*step*sample."""
     from paper_2503_12204_amd import workloads as W
     dx, du, dp = W.dims(dyn)
-    dyn_ops = {W.UNICYCLE: 13, W.DIFFDRIVE: 17}.get(dyn, 5 * dp)
-    broad = (n - 1) / 2.0 * (4 * dp + 2) / steps_per_block
-    return du * OPS_PER_NORMAL + 4 * du + dyn_ops + (2 * dp + 3) + 2 * dp + broad + 3
+    dyn_ops = {W.UNICYCLE: (6, 3, 4), W.DIFFDRIVE: (8, 5, 4)}.get(dyn, (3 * dp, 2 * dp, 0))
+    pairs = (n - 1) / 2.0 / steps_per_block
+    fma = du * NORMAL_OPS[0] + 2 * du + dyn_ops[0] + dp + pairs * dp
+    other = du * NORMAL_OPS[1] + 2 * du + dyn_ops[1] + (dp + 2) + 2 * dp + pairs * (3 * dp + 2) + 3
+    trans = du * NORMAL_OPS[2] + dyn_ops[2] + 1
+    return fma, other, trans
+
+
+def issue_seconds_per_unit(ops):
+    """Ideal VALU time of one robot*step*sample at the issue rates above."""
+    fma, other, trans = ops
+    return fma / FMA_RATE + other / OTHER_RATE + trans / TRANS_RATE
 
 
 WORKLOADS = {
@@ -227,8 +249,10 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="only launch the fused kernel this many times (for counter runs)")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
-    ap.add_argument("--experiment", choices=["batched", "proposal"], default=None,
-                    help="time-to-target of the batched or learned-proposal form against the plain planner")
+    ap.add_argument("--experiment", choices=["batched", "proposal", "sensitivity"], default=None,
+                    help="time-to-target of the batched or learned-proposal form against the plain planner, "
+                         "or the success-rate sweep over denoising steps and iterations")
+    ap.add_argument("--runs", type=int, default=30, help="runs per cell of the sensitivity sweep")
     ap.add_argument("--train-teams", type=int, default=4096)
     ap.add_argument("--test-teams", type=int, default=1000)
     ap.add_argument("--epochs", type=int, default=20)
@@ -259,6 +283,16 @@ def main():
                    "dtype": "f32", "data": "synthetic",
                    "config": {"workload": "batched_mix", "description": "512 instances, robots U{2..32}, "
                               "horizon U{40..160}, 3 dynamics, M=1024, N=100, random starts/goals in a 10 m box"},
+                   "details": res}
+        elif args.experiment == "sensitivity":
+            res = E.sensitivity(L, runs=args.runs, log=log)
+            mid = [c for c in res["cells"] if c["denoising_steps"] == 100]
+            out = {"metric": "success rate within the iteration budget, mean over dynamics and team sizes at N=100",
+                   "value": float(np.mean([c["success_within_iterations"][-1] for c in mid])), "unit": "fraction",
+                   "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": "sensitivity", "description": "antipodal circle (sphere in 3D) teams of "
+                              "10 and 16 robots, differential drive / 2D / 3D holonomic, T=100, M=2048, "
+                              "N in {50, 100, 200, 300}, 5 iterations, independent runs per cell"},
                    "details": res}
         else:
             res = E.proposal_gain(L, n_train=args.train_teams, n_test=args.test_teams, epochs=args.epochs, log=log)
@@ -313,13 +347,17 @@ def main():
     t_k = time_fused_kernel_in_iteration(L, p, x0, g, u, args.warmup + args.steps + 1)
     from paper_2503_12204_amd import autotune as AT
     S_t, Tb_t, R_t = AT.get_tile(p)
-    opu = ops_per_unit(p.dyn, p.n_robots, Tb_t)
-    ops = opu * p.n_robots * p.horizon * p.n_samples
-    achieved = ops / t_k
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK, "traffic": stored_traffic(args.workload),
+    opc = ops_per_unit(p.dyn, p.n_robots, Tb_t)
+    opu = sum(opc)
+    units = p.n_robots * p.horizon * p.n_samples
+    achieved = opu * units / t_k
+    # the peak for this mix: its operations over their ideal issue time
+    peak = opu / issue_seconds_per_unit(opc)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "T lane-ops/s", "frac": achieved / peak, "traffic": stored_traffic(args.workload),
                 "kernel": "k_rollfit (fused sample+rollout+reward)", "kernel_us": t_k * 1e6,
-                "ops_per_unit": opu, "tile": {"samples_per_group": S_t, "steps_per_block": Tb_t,
+                "ops_per_unit": opu, "ops_per_unit_fma_other_trans": list(opc),
+                "tile": {"samples_per_group": S_t, "steps_per_block": Tb_t,
                                               "replicas": R_t}}
     # the weighted reduction: HBM-bound; algorithmic bytes = the draws read
     # once, the rewards, Delta U in and out, and the weights written once

@@ -25,57 +25,109 @@ constexpr int MAX_OBS = 16;   // static obstacles per problem
 enum { FLAG_NORMALIZE = 1, FLAG_SAFE_PAIRS = 2 };
 
 // ------------------------------------------------------------------ Philox
-__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
-                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+// Philox4x32-10 on G independent counter blocks under one key.  The rounds
+// run in lockstep across the blocks: each round is a short dependent chain
+// (two 32x32->64 products feeding two three-input XORs), so interleaving
+// the blocks keeps 2G products in flight instead of two.
+template <int G>
+__device__ __forceinline__ void philox4x32_10_n(uint32_t (&c)[G][4], uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
-        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        // three-input XORs (truth table 0x96) in one gfx950 instruction each
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
-        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const uint64_t p0 = (uint64_t)0xD2511F53u * c[q][0];
+            const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[q][2];
+            const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+            const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
+            // three-input XORs (truth table 0x96) in one gfx950 instruction each
+            const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c[q][1], k0, 0x96);
+            const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c[q][3], k1, 0x96);
+            c[q][0] = n0;
+            c[q][1] = lo1;
+            c[q][2] = n2;
+            c[q][3] = lo0;
+        }
     }
 }
 
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+    uint32_t c[1][4] = {{c0, c1, c2, c3}};
+    philox4x32_10_n<1>(c, k0, k1);
+    c0 = c[0][0];
+    c1 = c[0][1];
+    c2 = c[0][2];
+    c3 = c[0][3];
+}
+
 // ------------------------------------------------ FP32 ln and sin/cos recipe
+// Each function below works on P independent operands, one operation at a
+// time across all of them (the per-operand sequence does not depend on P),
+// so that P dependent chains are in flight together.
+
 // Correctly rounded a / b for the operands of ln_unit (a in [-0.25, 0.5],
 // b in [1.75, 2.5]): the reciprocal refinement and the two residual
 // corrections of the full IEEE division sequence, without its range scaling
 // and special-value fix-up, which are identities for finite operands of
 // moderate exponent.  Every reachable operand pair is checked against the
 // correctly rounded quotient by the exhaustive transform test.
+template <int P>
+__device__ __forceinline__ void div_rn_moderate_n(const float (&a)[P], const float (&b)[P], float (&out)[P]) {
+    float y[P], e[P], q[P], r[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) y[i] = __builtin_amdgcn_rcpf(b[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) e[i] = __builtin_fmaf(-b[i], y[i], 1.0f);
+#pragma unroll
+    for (int i = 0; i < P; ++i) y[i] = __builtin_fmaf(e[i], y[i], y[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) q[i] = a[i] * y[i];
+#pragma unroll
+    for (int i = 0; i < P; ++i) r[i] = __builtin_fmaf(-b[i], q[i], a[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) q[i] = __builtin_fmaf(r[i], y[i], q[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) r[i] = __builtin_fmaf(-b[i], q[i], a[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) out[i] = __builtin_fmaf(r[i], y[i], q[i]);
+}
+
 __device__ __forceinline__ float div_rn_moderate(float a, float b) {
-    float y = __builtin_amdgcn_rcpf(b);
-    const float e = __builtin_fmaf(-b, y, 1.0f);
-    y = __builtin_fmaf(e, y, y);
-    float q = a * y;
-    float r = __builtin_fmaf(-b, q, a);
-    q = __builtin_fmaf(r, y, q);
-    r = __builtin_fmaf(-b, q, a);
-    return __builtin_fmaf(r, y, q);
+    const float av[1] = {a}, bv[1] = {b};
+    float q[1];
+    div_rn_moderate_n<1>(av, bv, q);
+    return q[0];
 }
 
 // Correctly rounded sqrt(x) for finite normal x > 0 away from the denormal
 // range: the hardware estimate (within 1 ulp) is moved to a neighbour when the
 // exact residual x - s' s says that the neighbour is nearer.
+template <int P>
+__device__ __forceinline__ void sqrt_rn_normal_n(const float (&x)[P], float (&out)[P]) {
+    float sq[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) sq[i] = __builtin_amdgcn_sqrtf(x[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const float s = sq[i];
+        const float s_dn = __uint_as_float(__float_as_uint(s) - 1u);
+        const float s_up = __uint_as_float(__float_as_uint(s) + 1u);
+        const float r_dn = __builtin_fmaf(-s_dn, s, x[i]);
+        const float r_up = __builtin_fmaf(-s_up, s, x[i]);
+        const float o = r_dn <= 0.0f ? s_dn : s;
+        out[i] = r_up > 0.0f ? s_up : o;
+    }
+}
+
 __device__ __forceinline__ float sqrt_rn_normal(float x) {
-    const float s = __builtin_amdgcn_sqrtf(x);
-    const float s_dn = __uint_as_float(__float_as_uint(s) - 1u);
-    const float s_up = __uint_as_float(__float_as_uint(s) + 1u);
-    const float r_dn = __builtin_fmaf(-s_dn, s, x);
-    const float r_up = __builtin_fmaf(-s_up, s, x);
-    float out = r_dn <= 0.0f ? s_dn : s;
-    return r_up > 0.0f ? s_up : out;
+    const float xv[1] = {x};
+    float o[1];
+    sqrt_rn_normal_n<1>(xv, o);
+    return o[0];
 }
 
 // Natural log of a uniform in (0, 1): u = 2^e f, f in [0.75, 1.5),
@@ -83,23 +135,40 @@ __device__ __forceinline__ float sqrt_rn_normal(float x) {
 // fused Horner form through s^9, e*ln2 split as 355/512 (exact products
 // with e) plus the FP32 remainder.
 // Within 2 ulp of ln u for every uniform the recipe produces.
-__device__ __forceinline__ float ln_unit(float u) {
+template <int P>
+__device__ __forceinline__ void ln_unit_n(const float (&u)[P], float (&out)[P]) {
 #pragma clang fp contract(off)
     const float A3 = 1.0f / 3.0f, A5 = 1.0f / 5.0f, A7 = 1.0f / 7.0f, A9 = 1.0f / 9.0f;
     const float LN2_HI = 355.0f / 512.0f;
     const float LN2_LO = (float)(0.693147180559945309417232121458 - 355.0 / 512.0);
-    const uint32_t b = __float_as_uint(u);
-    int e = (int)(b >> 23) - 127;
-    float f = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
-    const bool big = f >= 1.5f;
-    f = big ? f * 0.5f : f;
-    e += big ? 1 : 0;
-    const float s = div_rn_moderate(f - 1.0f, f + 1.0f);
-    const float s2 = s * s;
-    const float q = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(A9, s2, A7), s2, A5), s2, A3);
-    const float t = __builtin_fmaf(s * s2, q, s);
-    const float ef = (float)e;
-    return __builtin_fmaf(ef, LN2_HI, __builtin_fmaf(ef, LN2_LO, 2.0f * t));
+    float num[P], den[P], ef[P], s[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const uint32_t b = __float_as_uint(u[i]);
+        int e = (int)(b >> 23) - 127;
+        float f = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
+        const bool big = f >= 1.5f;
+        f = big ? f * 0.5f : f;
+        e += big ? 1 : 0;
+        num[i] = f - 1.0f;
+        den[i] = f + 1.0f;
+        ef[i] = (float)e;
+    }
+    div_rn_moderate_n<P>(num, den, s);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const float s2 = s[i] * s[i];
+        const float q = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(A9, s2, A7), s2, A5), s2, A3);
+        const float t = __builtin_fmaf(s[i] * s2, q, s[i]);
+        out[i] = __builtin_fmaf(ef[i], LN2_HI, __builtin_fmaf(ef[i], LN2_LO, 2.0f * t));
+    }
+}
+
+__device__ __forceinline__ float ln_unit(float u) {
+    const float uv[1] = {u};
+    float o[1];
+    ln_unit_n<1>(uv, o);
+    return o[0];
 }
 
 // sin and cos of 2 pi u_b for u_b = (2j + 1) 2^-24, j = word >> 9: exact
@@ -129,26 +198,78 @@ __device__ __forceinline__ void sincos_2pi_word(uint32_t word, float& sn_o, floa
     cs_o = __uint_as_float(__float_as_uint(b) ^ (((qq + 1u) & 2u) << 30));
 }
 
-// rho = sqrt(-2 ln u_a) lies in [3e-4, 5.8]: its square is a normal FP32
-// number, so sqrt_rn_normal applies.
-__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z_even, float& z_odd) {
+// Box-Muller on P word pairs: rho = sqrt(-2 ln u_a) lies in [3e-4, 5.8], so
+// its square is a normal FP32 number and sqrt_rn_normal applies.  The
+// sin/cos of each pair has no dependence on its ln and sqrt chain.
+template <int P>
+__device__ __forceinline__ void box_muller_n(const uint32_t (&wa)[P], const uint32_t (&wb)[P],
+                                             float (&z_even)[P], float (&z_odd)[P]) {
 #pragma clang fp contract(off)
-    const float u = (float)(((wa >> 9) << 1) + 1u) * 0x1.0p-24f;
-    const float rho = sqrt_rn_normal(-2.0f * ln_unit(u));
-    float s, c;
-    sincos_2pi_word(wb, s, c);
-    z_even = rho * c;
-    z_odd = rho * s;
+    float u[P], l[P], rho[P], sn[P], cs[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[i] = (float)(((wa[i] >> 9) << 1) + 1u) * 0x1.0p-24f;
+    ln_unit_n<P>(u, l);
+#pragma unroll
+    for (int i = 0; i < P; ++i) l[i] = -2.0f * l[i];
+    sqrt_rn_normal_n<P>(l, rho);
+#pragma unroll
+    for (int i = 0; i < P; ++i) sincos_2pi_word(wb[i], sn[i], cs[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        z_even[i] = rho[i] * cs[i];
+        z_odd[i] = rho[i] * sn[i];
+    }
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z_even, float& z_odd) {
+    const uint32_t a[1] = {wa}, b[1] = {wb};
+    float ze[1], zo[1];
+    box_muller_n<1>(a, b, ze, zo);
+    z_even = ze[0];
+    z_odd = zo[0];
+}
+
+// The 4G normals of the consecutive Philox blocks group0 .. group0+G-1 of
+// sample m, block q's four normals at z[4q .. 4q+3].
+template <int G>
+__device__ __forceinline__ void normal_blocks(uint32_t group0, uint32_t m, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, float* z) {
+    uint32_t w[G][4];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        w[q][0] = group0 + (uint32_t)q;
+        w[q][1] = m;
+        w[q][2] = c2;
+        w[q][3] = c3;
+    }
+    philox4x32_10_n<G>(w, k0, k1);
+    uint32_t wa[2 * G], wb[2 * G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        wa[2 * q] = w[q][0];
+        wb[2 * q] = w[q][1];
+        wa[2 * q + 1] = w[q][2];
+        wb[2 * q + 1] = w[q][3];
+    }
+    float ze[2 * G], zo[2 * G];
+    box_muller_n<2 * G>(wa, wb, ze, zo);
+#pragma unroll
+    for (int j = 0; j < 2 * G; ++j) {
+        z[2 * j] = ze[j];
+        z[2 * j + 1] = zo[j];
+    }
 }
 
 // The four normals of Philox block `group` for sample m.
 __device__ __forceinline__ void normal_block(uint32_t group, uint32_t m, uint32_t c2, uint32_t c3,
                                              uint32_t k0, uint32_t k1, float& z0, float& z1,
                                              float& z2, float& z3) {
-    uint32_t w0 = group, w1 = m, w2 = c2, w3 = c3;
-    philox4x32_10(w0, w1, w2, w3, k0, k1);
-    box_muller(w0, w1, z0, z1);
-    box_muller(w2, w3, z2, z3);
+    float z[4];
+    normal_blocks<1>(group, m, c2, c3, k0, k1, z);
+    z0 = z[0];
+    z1 = z[1];
+    z2 = z[2];
+    z3 = z[3];
 }
 
 // Square root outside the bit-exact recipe (goal distances): one hardware

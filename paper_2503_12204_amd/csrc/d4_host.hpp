@@ -176,12 +176,13 @@ struct Tile {
 // rule serves the single-problem and the batched kernels (workgroups of at most
 // 256 lanes), so a batched instance reproduces its single-problem run bit for
 // bit: S = min(64, floor(256 / n)) samples, and a time block that keeps the
-// positions near 64 KiB, in whole draw chunks.
+// positions near 32 KiB, in whole draw chunks, so that three workgroups share
+// a CU's 160 KiB of LDS.
 inline Tile default_tile(int dyn, int n) {
     int S = std::min(64, 256 / n);
     const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
-    const int per_step = (2 * n - 1) * S * slot;
-    int Tb = (64 * 1024) / per_step;
+    const int per_step = n * S * slot;
+    int Tb = (32 * 1024) / per_step;
     const int cs = shape_of(dyn).du == 2 ? 2 : 4;
     Tb = std::max(cs, std::min(16, Tb / cs * cs));
     return {S, Tb};
@@ -201,7 +202,7 @@ inline Tile single_tile(int dyn, int n, int M) {
     const int R = std::max(1, std::min(4, 256 / (S * n)));
     const int cs = shape_of(dyn).du == 2 ? 2 : 4;
     const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
-    const int Tb = R > 1 ? 16 : std::max(cs, std::min(16, ((64 * 1024) / ((2 * n - 1) * S * slot)) / cs * cs));
+    const int Tb = R > 1 ? 16 : std::max(cs, std::min(16, ((32 * 1024) / (n * S * slot)) / cs * cs));
     Tile out;
     out.S = S;
     out.Tb = Tb;
@@ -252,8 +253,8 @@ inline size_t rollfit_lds(const d4_problem* p, Tile t) {
         const size_t b = (size_t)(3 + t.R) * n * t.S * 4;
         return a > b ? a : b;
     }
-    // one-lane kernel: positions [Tb][2n-1][S], boxes [n][S][2], masks [2][Tb][S], flags [2][S]
-    const size_t a = (size_t)t.Tb * n2 * t.S * slot + (size_t)2 * n * t.S * slot +
+    // one-lane kernel: positions [Tb][n][S], boxes [n][S][2], masks [2][Tb][S], flags [2][S]
+    const size_t a = (size_t)t.Tb * n * t.S * slot + (size_t)2 * n * t.S * slot +
                      (size_t)2 * t.Tb * t.S * 4 + (size_t)2 * t.S * 4;
     const size_t b = (size_t)4 * n * t.S * 4;
     return a > b ? a : b;

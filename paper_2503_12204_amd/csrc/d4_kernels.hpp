@@ -13,9 +13,10 @@
 // Lane mapping of k_rollfit: one lane per (sample m, robot k) with the sample
 // index fastest, S samples per workgroup (blockDim = n*S).  A lane keeps its
 // robot's state in registers and walks t = 0..T-1; positions of a block of Tb
-// steps go to LDS as [Tb][2n-1][S] float2/float4 slots (robots 0..n-1, then
-// 0..n-2 again, so a lane's partners are contiguous) and the pair checks of
-// one step read consecutive slots across a wave.  Lane k checks partners (k + j) mod n
+// steps go to LDS as [Tb][n][S] float2/float4 slots, one per robot and step
+// (the small footprint keeps three 256-lane workgroups on a CU at Tb = 8 for
+// 16 robots in space), and the pair checks of one step read consecutive slots
+// across a wave.  Lane k checks partners (k + j) mod n
 // for j = 1..floor((n-1)/2), plus j = n/2 for k < n/2 when n is even: every
 // unordered pair exactly once, spread evenly.  Each lane also keeps the
 // bounding box of its positions over the block; a partner is checked step by
@@ -171,6 +172,27 @@ __device__ __forceinline__ uint32_t pair_bits_near(const typename PosSlot<DP>::T
     return (uint32_t)((bits | (bits >> n)) & low);
 }
 
+// As pair_bits_near for positions stored once per robot ([n][S] per step):
+// partner j of robot k is robot (k + 1 + j) mod n, and a hit sets its bit.
+template <int DP>
+__device__ __forceinline__ uint32_t pair_bits_near_wrap(const typename PosSlot<DP>::T* pb, int n, int S, int k,
+                                                        uint32_t near, float thr2) {
+    using PS = PosSlot<DP>;
+    float pk[DP];
+    PS::unpack(pb[k * S], pk);
+    uint32_t bits = 0u;
+    while (near) {
+        const int j = __builtin_ctz(near);
+        near &= near - 1u;
+        int l = k + 1 + j;
+        l = l >= n ? l - n : l;
+        float pl[DP];
+        PS::unpack(pb[l * S], pl);
+        if (pair_d2<DP>(pk, pl) <= thr2) bits |= 1u << l;
+    }
+    return bits;
+}
+
 // Steps per noise chunk (a whole number of Philox blocks) and blocks per chunk.
 template <int DU>
 struct Chunk {
@@ -199,9 +221,8 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     const int m = m0 + ms;
     const bool live = active && m < M;
     const int mc = m < M ? m : M - 1;
-    const int n2 = 2 * n - 1;                                                    // slots per step
-    PT* pos = reinterpret_cast<PT*>(lds);                                        // [Tb][2n-1][S]
-    PT* box = pos + Tb * n2 * S;                                                 // [n][S][lo, hi]
+    PT* pos = reinterpret_cast<PT*>(lds);                                        // [Tb][n][S]
+    PT* box = pos + Tb * n * S;                                                  // [n][S][lo, hi]
     uint32_t* mask = reinterpret_cast<uint32_t*>(box + 2 * n * S);              // [2][Tb][S]
     uint32_t* anyhit = mask + 2 * Tb * S;                                        // [2][S]
 
@@ -266,9 +287,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
         }
         if (active) {
             const PT v = PS::pack(x);
-            PT* slot = pos + (tt * n2 + k) * S + ms;
-            slot[0] = v;
-            if (k < n - 1) slot[n * S] = v;
+            pos[(tt * n + k) * S + ms] = v;
         }
     };
 
@@ -319,10 +338,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                 float win[4 + 4 * CG];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) win[j] = left[j];
-#pragma unroll
-                for (int q = 0; q < CG; ++q)
-                    normal_block(g0 + 1 + q, (uint32_t)mc, c2, a.inst, a.key0, a.key1, win[4 + 4 * q],
-                                 win[5 + 4 * q], win[6 + 4 * q], win[7 + 4 * q]);
+                normal_blocks<CG>(g0 + 1, (uint32_t)mc, c2, a.inst, a.key0, a.key1, win + 4);
                 float z[4 * CG];
 #pragma unroll
                 for (int j = 0; j < 4 * CG; ++j)
@@ -395,7 +411,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
         if (near) {
             bool any = false;
             for (int tt = 0; tt < tcount; ++tt) {
-                const uint32_t bits = pair_bits_near<DP>(pos + tt * n2 * S + ms, n, S, k, near, a.thr2);
+                const uint32_t bits = pair_bits_near_wrap<DP>(pos + tt * n * S + ms, n, S, k, near, a.thr2);
                 hit_cnt += __popc(bits);
                 if (bits) {
                     atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));

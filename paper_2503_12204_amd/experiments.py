@@ -152,3 +152,57 @@ def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=
     }
     prop.close()
     return out
+
+
+SENSITIVITY_DYNAMICS = {
+    "diffdrive": W.diffdrive_circle,
+    "holo2d": W.holo2d_circle,
+    "holo3d": W.holo3d_sphere,
+}
+
+
+def sensitivity(L, dynamics=("diffdrive", "holo2d", "holo3d"), teams=(10, 16), steps=(50, 100, 200, 300),
+                iterations=5, runs=30, n_samples=2048, horizon=100, log=print):
+    """Success rate against N and the iteration count (Sec. V-B, Fig. 2).
+
+    One cell is (dynamics, team size, N).  Its runs are the same antipodal
+    team (circle in the plane, sphere in space) with independent draws: run j
+    is instance j of one batch, so its Philox stream differs from every other
+    run's.  A run counts as solved within k iterations when any of its first
+    k iterations ends conflict-free (the problem's conditions, Sec. III: the
+    controls are feasible by construction); the planner returns the first such
+    plan, so the rate cannot fall as k grows.  The rate of plans that also end
+    within the goal tolerance is reported beside it."""
+    cells = []
+    for dyn in dynamics:
+        build = SENSITIVITY_DYNAMICS[dyn]
+        for n in teams:
+            for n_steps in steps:
+                p, x0, goal = build(n=n, horizon=horizon, n_samples=n_samples, n_steps=n_steps)
+                probs = [p.replace(instance_id=j) for j in range(runs)]
+                bc = L.BatchContext(probs, [x0] * runs, [goal] * runs)
+                solved = np.zeros(runs, dtype=bool)
+                arrived = np.zeros(runs, dtype=bool)
+                rate, goal_rate, reward, hits = [], [], [], []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for k in range(iterations):
+                    st = bc.iterate(k)
+                    ok = np.array([s["success"] for s in st], dtype=bool)
+                    at = np.array([s["at_goal"] for s in st], dtype=bool)
+                    solved |= ok
+                    arrived |= ok & at
+                    rate.append(float(solved.mean()))
+                    goal_rate.append(float(arrived.mean()))
+                    reward.append(float(np.mean([s["reward"] for s in st])))
+                    hits.append(float(np.mean([s["hits"] for s in st])))
+                secs = (time.perf_counter() - t0) / iterations
+                bc.close()
+                cells.append({"dynamics": dyn, "robots": n, "denoising_steps": n_steps,
+                              "success_within_iterations": rate, "success_at_goal_within_iterations": goal_rate,
+                              "mean_reward_after_iteration": reward, "mean_hits_after_iteration": hits,
+                              "seconds_per_iteration_all_runs": secs})
+                log(f"{dyn} n={n} N={n_steps}: success within 1..{iterations} iterations "
+                    + " ".join(f"{r:.2f}" for r in rate) + f"  ({secs * 1e3:.0f} ms per iteration of {runs} runs)")
+    return {"runs_per_cell": runs, "samples": n_samples, "horizon": horizon, "iterations": iterations,
+            "denoising_steps": list(steps), "teams": list(teams), "dynamics": list(dynamics), "cells": cells}

@@ -67,3 +67,29 @@ def test_batch_rejects_mixed_sampler_settings(L):
     probs = [inst[0][0], inst[1][0].replace(temperature=0.2)]
     with pytest.raises(L.D4Error):
         L.BatchContext(probs, [x for _, x, _ in inst], [g for _, _, g in inst])
+
+
+def test_sensitivity_sweep_cells(L):
+    """The success-rate sweep (Sec. V-B) on a tiny grid: one cell per
+    (dynamics, team, N), rates that never fall with more iterations, and
+    independent draws per run."""
+    from paper_2503_12204_amd import experiments as E
+    print("sensitivity sweep: 3 dynamics x n=4 x N in {6, 12}, 3 runs, M=128, T=16", flush=True)
+    res = E.sensitivity(L, teams=(4,), steps=(6, 12), iterations=3, runs=3, n_samples=128, horizon=16,
+                        log=lambda m: print(m, flush=True))
+    cells = res["cells"]
+    assert [(c["dynamics"], c["denoising_steps"]) for c in cells] == [
+        (d, N) for d in ("diffdrive", "holo2d", "holo3d") for N in (6, 12)]
+    for c in cells:
+        rate, at = c["success_within_iterations"], c["success_at_goal_within_iterations"]
+        assert len(rate) == 3 and all(0.0 <= r <= 1.0 for r in rate)
+        assert all(b >= a for a, b in zip(rate, rate[1:]))
+        assert all(g <= r for g, r in zip(at, rate))
+        assert all(np.isfinite(c["mean_reward_after_iteration"]))
+    # runs of one cell use different instance ids, so their plans differ
+    p, x0, goal = W.holo2d_circle(n=4, horizon=16, n_samples=128, n_steps=6)
+    bc = L.BatchContext([p.replace(instance_id=j) for j in range(2)], [x0] * 2, [goal] * 2)
+    bc.iterate(0)
+    a, b = bc.plan_of(0).cpu().numpy(), bc.plan_of(1).cpu().numpy()
+    bc.close()
+    assert not np.array_equal(a, b)
