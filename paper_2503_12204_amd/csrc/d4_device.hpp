@@ -272,6 +272,26 @@ __device__ __forceinline__ void normal_block(uint32_t group, uint32_t m, uint32_
     z3 = z[3];
 }
 
+// min(max(x, lo), hi) for lo <= hi: the median of the three, one v_med3_f32
+// (fminf/fmaxf would first quiet each operand, as IEEE minNum/maxNum ask).
+// Equal to the clamp for every finite x.
+__device__ __forceinline__ float clamp_f(float x, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+// Running min and max of finite values as medians with -inf and +inf (no
+// operand quieting, unlike fminf/fmaxf).  The infinities come from scalar
+// register moves the optimiser cannot see through, which keeps it from
+// folding the medians back into minnum/maxnum.
+struct MinMaxInf {
+    float ninf, pinf;
+    __device__ __forceinline__ MinMaxInf() {
+        asm volatile("s_mov_b32 %0, 0xff800000" : "=s"(ninf));
+        asm volatile("s_mov_b32 %0, 0x7f800000" : "=s"(pinf));
+    }
+    __device__ __forceinline__ float min(float a, float b) const { return __builtin_amdgcn_fmed3f(a, b, ninf); }
+    __device__ __forceinline__ float max(float a, float b) const { return __builtin_amdgcn_fmed3f(a, b, pinf); }
+};
+
 // Square root outside the bit-exact recipe (goal distances): one hardware
 // v_sqrt_f32 (1 ulp) instead of the correctly rounded sequence.
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -312,7 +332,7 @@ __device__ __forceinline__ float sample_mean(float ub, float du, float mscale) {
     return __builtin_fmaf(du, mscale, ub);
 }
 __device__ __forceinline__ float sample_from_mean(float mean, float sigma, float z, float lo, float hi) {
-    return fminf(fmaxf(__builtin_fmaf(sigma, z, mean), lo), hi);
+    return clamp_f(__builtin_fmaf(sigma, z, mean), lo, hi);
 }
 __device__ __forceinline__ float sample_control(float ub, float du, float mscale, float sigma, float z, float lo,
                                                 float hi) {
@@ -342,7 +362,7 @@ struct Dyn<HOLO2D> {
         for (int i = 0; i < 2; ++i) {
             const float p = x[i], v = x[2 + i], a = u[i];
             x[i] = __builtin_fmaf(a, c.hdt2, __builtin_fmaf(v, c.dt, p));
-            x[2 + i] = fminf(fmaxf(__builtin_fmaf(a, c.dt, v), -c.vmax), c.vmax);
+            x[2 + i] = clamp_f(__builtin_fmaf(a, c.dt, v), -c.vmax, c.vmax);
         }
     }
 };
@@ -357,7 +377,7 @@ struct Dyn<HOLO3D> {
         for (int i = 0; i < 3; ++i) {
             const float p = x[i], v = x[3 + i], a = u[i];
             x[i] = __builtin_fmaf(a, c.hdt2, __builtin_fmaf(v, c.dt, p));
-            x[3 + i] = fminf(fmaxf(__builtin_fmaf(a, c.dt, v), -c.vmax), c.vmax);
+            x[3 + i] = clamp_f(__builtin_fmaf(a, c.dt, v), -c.vmax, c.vmax);
         }
     }
 };
@@ -414,7 +434,7 @@ struct Dyn<DIFFDRIVE> {
         x[0] = __builtin_fmaf(c.dt6, __builtin_fmaf(4.0f * vh, ch, v0 * aux[0]) + v1 * c1, x[0]);
         x[1] = __builtin_fmaf(c.dt6, __builtin_fmaf(4.0f * vh, sh, v0 * aux[1]) + v1 * s1, x[1]);
         x[2] = th_1;
-        x[3] = fminf(fmaxf(v1, -c.vmax), c.vmax);
+        x[3] = clamp_f(v1, -c.vmax, c.vmax);
         aux[0] = c1;
         aux[1] = s1;
     }

@@ -275,6 +275,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
 
     // bounding box of this lane's positions over the current block
     float blo[DP], bhi[DP];
+    const MinMaxInf mm;
 
     // goal term, LDS position and bounding box of the state after step tt of the block
     auto after_step = [&](int tt) {
@@ -282,8 +283,8 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
         if (n_obs) obs_cnt += obstacle_hit<DP>(x, obs_l, n_obs);
 #pragma unroll
         for (int c = 0; c < DP; ++c) {
-            blo[c] = fminf(blo[c], x[c]);
-            bhi[c] = fmaxf(bhi[c], x[c]);
+            blo[c] = mm.min(blo[c], x[c]);
+            bhi[c] = mm.max(bhi[c], x[c]);
         }
         if (active) {
             const PT v = PS::pack(x);
