@@ -151,29 +151,10 @@ __device__ __forceinline__ uint32_t pair_bits(const typename PosSlot<DP>::T* pb,
     return (uint32_t)((bits | (bits >> n)) & low);
 }
 
-// As pair_bits, for the partners j (bit j of near) that the block's bounding
-// boxes could not rule out; the remaining partners hold no hit in this block.
-template <int DP>
-__device__ __forceinline__ uint32_t pair_bits_near(const typename PosSlot<DP>::T* pb, int n, int S, int k,
-                                                   uint32_t near, float thr2) {
-    using PS = PosSlot<DP>;
-    float pk[DP];
-    PS::unpack(pb[k * S], pk);
-    const typename PS::T* q = pb + (k + 1) * S;
-    uint64_t bits = 0ull;
-    while (near) {
-        const int j = __builtin_ctz(near);
-        near &= near - 1u;
-        float pl[DP];
-        PS::unpack(q[j * S], pl);
-        if (pair_d2<DP>(pk, pl) <= thr2) bits |= 2ull << (k + j);
-    }
-    const uint64_t low = n >= 32 ? 0xFFFFFFFFull : ((1ull << n) - 1ull);
-    return (uint32_t)((bits | (bits >> n)) & low);
-}
-
-// As pair_bits_near for positions stored once per robot ([n][S] per step):
-// partner j of robot k is robot (k + 1 + j) mod n, and a hit sets its bit.
+// Hit bits of robot k at one step against the partners j (bit j of near)
+// that the block's bounding boxes could not rule out; the remaining partners
+// hold no hit in this block.  Positions are stored once per robot ([n][S] per
+// step): partner j of robot k is robot (k + 1 + j) mod n, and a hit sets its bit.
 template <int DP>
 __device__ __forceinline__ uint32_t pair_bits_near_wrap(const typename PosSlot<DP>::T* pb, int n, int S, int k,
                                                         uint32_t near, float thr2) {
