@@ -580,7 +580,7 @@ int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int
     float best = 1e30f;
     Tile best_t = default_tile(p->dyn, p->n_robots);
     const int cs = s.du == 2 ? 2 : 4;
-    for (int R : {1, 2, 4}) for (int S : {4, 8, 16, 32, 64}) {
+    for (int R : {1, 2, 4, 8}) for (int S : {4, 8, 16, 32, 64}) {
         for (int Tb : {2, 4, 8, 12, 16, 32}) {
             Tile t;
             t.S = S;
