@@ -32,6 +32,9 @@ struct d4_batch {
 
 namespace {
 
+// dynamic LDS of a reward workgroup that leaves room for two, not three, on a CU
+constexpr size_t LDS_TWO_PER_CU = 56 * 1024;
+
 bool same_sampler(const d4_problem& a, const d4_problem& b) {
     return a.n_samples == b.n_samples && a.n_steps == b.n_steps && a.temperature == b.temperature &&
            a.beta_min == b.beta_min && a.beta_max == b.beta_max && a.flags == b.flags && a.seed == b.seed;
@@ -214,7 +217,11 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
     b->tot_eps = oe;
     b->tot_r = orr;
     b->tot_traj = ot;
-    b->lds_rollfit = lds;
+    // At most two reward workgroups per CU: the batched kernel carries every
+    // dynamics and draw alignment, and three workgroups of a mixed batch on a
+    // CU ran 45 % slower than two (one per CU ran slower still).  Requesting
+    // more than a third of the CU's LDS enforces the limit.
+    b->lds_rollfit = std::max(lds, LDS_TWO_PER_CU);
     if (ou >= (1ll << 31) || oe >= (1ll << 40)) {
         delete b;
         return fail(D4_EUNSUPPORTED, "batch too large");
