@@ -84,3 +84,20 @@ def test_null_and_misaligned_pointers_rejected(L):
     assert L.lib().d4_box_muller(None, 4, ctypes.cast(buf, ctypes.c_void_p), None) == L.D4_EINVAL
     assert L.lib().d4_box_muller(ctypes.cast(buf, ctypes.c_void_p), 4, odd, None) == L.D4_EINVAL
     assert L.lib().d4_box_muller(None, 0, None, None) == L.D4_OK
+
+
+def test_invalid_obstacles_rejected_without_launch(L):
+    """Obstacles (appendix penalty): a count outside 0..16, a non-finite
+    centre or a negative radius fail before any launch."""
+    from paper_2503_12204_amd import workloads as W
+    p, _, _ = W.holo2d_circle_obstacles(n=4, n_obs=2)
+    buf = (ctypes.c_float * 4)()
+    out = ctypes.cast(buf, ctypes.c_void_p)
+    for mutate in (lambda c: setattr(c, "n_obstacles", L.MAX_OBSTACLES + 1),
+                   lambda c: setattr(c, "n_obstacles", -1),
+                   lambda c: c.obstacles[1].__setitem__(0, float("nan")),
+                   lambda c: c.obstacles[0].__setitem__(3, -0.5)):
+        c = L.to_c(p)
+        mutate(c)
+        assert L.lib().d4_noise(ctypes.byref(c), 0, 1, out, None) == L.D4_EINVAL
+        assert L.lib().d4_last_error().decode()
