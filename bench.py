@@ -253,6 +253,9 @@ def main():
                     help="time-to-target of the batched or learned-proposal form against the plain planner, "
                          "or the success-rate sweep over denoising steps and iterations")
     ap.add_argument("--runs", type=int, default=30, help="runs per cell of the sensitivity sweep")
+    ap.add_argument("--radius", type=float, default=2.0, help="circle (sphere) radius of the sensitivity sweep, m")
+    ap.add_argument("--dynamics", default="diffdrive,holo2d,holo3d", help="dynamics of the sensitivity sweep")
+    ap.add_argument("--teams", default="10,16", help="team sizes of the sensitivity sweep")
     ap.add_argument("--train-teams", type=int, default=4096)
     ap.add_argument("--test-teams", type=int, default=1000)
     ap.add_argument("--epochs", type=int, default=20)
@@ -285,13 +288,15 @@ def main():
                               "horizon U{40..160}, 3 dynamics, M=1024, N=100, random starts/goals in a 10 m box"},
                    "details": res}
         elif args.experiment == "sensitivity":
-            res = E.sensitivity(L, runs=args.runs, log=log)
+            res = E.sensitivity(L, dynamics=tuple(args.dynamics.split(",")),
+                                teams=tuple(int(t) for t in args.teams.split(",")), runs=args.runs,
+                                radius=args.radius, log=log)
             mid = [c for c in res["cells"] if c["denoising_steps"] == 100]
             out = {"metric": "success rate within the iteration budget, mean over dynamics and team sizes at N=100",
                    "value": float(np.mean([c["success_within_iterations"][-1] for c in mid])), "unit": "fraction",
                    "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-                   "config": {"workload": "sensitivity", "description": "antipodal circle (sphere in 3D) teams of "
-                              "10 and 16 robots, differential drive / 2D / 3D holonomic, T=100, M=2048, "
+                   "config": {"workload": "sensitivity", "description": f"antipodal circle (sphere in 3D) of radius "
+                              f"{args.radius} m, teams of {args.teams} robots, dynamics {args.dynamics}, T=100, M=2048, "
                               "N in {50, 100, 200, 300}, 5 iterations, independent runs per cell"},
                    "details": res}
         else:

@@ -162,7 +162,7 @@ SENSITIVITY_DYNAMICS = {
 
 
 def sensitivity(L, dynamics=("diffdrive", "holo2d", "holo3d"), teams=(10, 16), steps=(50, 100, 200, 300),
-                iterations=5, runs=30, n_samples=2048, horizon=100, log=print):
+                iterations=5, runs=30, n_samples=2048, horizon=100, radius=2.0, log=print):
     """Success rate against N and the iteration count (Sec. V-B, Fig. 2).
 
     One cell is (dynamics, team size, N).  Its runs are the same antipodal
@@ -178,7 +178,7 @@ def sensitivity(L, dynamics=("diffdrive", "holo2d", "holo3d"), teams=(10, 16), s
         build = SENSITIVITY_DYNAMICS[dyn]
         for n in teams:
             for n_steps in steps:
-                p, x0, goal = build(n=n, horizon=horizon, n_samples=n_samples, n_steps=n_steps)
+                p, x0, goal = build(n=n, horizon=horizon, n_samples=n_samples, n_steps=n_steps, radius=radius)
                 probs = [p.replace(instance_id=j) for j in range(runs)]
                 bc = L.BatchContext(probs, [x0] * runs, [goal] * runs)
                 solved = np.zeros(runs, dtype=bool)
@@ -204,5 +204,5 @@ def sensitivity(L, dynamics=("diffdrive", "holo2d", "holo3d"), teams=(10, 16), s
                               "seconds_per_iteration_all_runs": secs})
                 log(f"{dyn} n={n} N={n_steps}: success within 1..{iterations} iterations "
                     + " ".join(f"{r:.2f}" for r in rate) + f"  ({secs * 1e3:.0f} ms per iteration of {runs} runs)")
-    return {"runs_per_cell": runs, "samples": n_samples, "horizon": horizon, "iterations": iterations,
+    return {"runs_per_cell": runs, "samples": n_samples, "horizon": horizon, "iterations": iterations, "radius": radius,
             "denoising_steps": list(steps), "teams": list(teams), "dynamics": list(dynamics), "cells": cells}
