@@ -249,11 +249,12 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="only launch the fused kernel this many times (for counter runs)")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
-    ap.add_argument("--experiment", choices=["batched", "proposal", "sensitivity"], default=None,
+    ap.add_argument("--experiment", choices=["batched", "proposal", "sensitivity", "first_success"], default=None,
                     help="time-to-target of the batched or learned-proposal form against the plain planner, "
                          "or the success-rate sweep over denoising steps and iterations")
     ap.add_argument("--runs", type=int, default=30, help="runs per cell of the sensitivity sweep")
-    ap.add_argument("--radius", type=float, default=2.0, help="circle (sphere) radius of the sensitivity sweep, m")
+    ap.add_argument("--radius", type=float, default=None,
+                    help="circle (sphere) radius, m: 2 for the sensitivity sweep, 4 for first_success by default")
     ap.add_argument("--dynamics", default="diffdrive,holo2d,holo3d", help="dynamics of the sensitivity sweep")
     ap.add_argument("--teams", default="10,16", help="team sizes of the sensitivity sweep")
     ap.add_argument("--train-teams", type=int, default=4096)
@@ -287,16 +288,27 @@ def main():
                    "config": {"workload": "batched_mix", "description": "512 instances, robots U{2..32}, "
                               "horizon U{40..160}, 3 dynamics, M=1024, N=100, random starts/goals in a 10 m box"},
                    "details": res}
+        elif args.experiment == "first_success":
+            res = [E.first_success(L, scenario=sc, n=t, radius=args.radius or 4.0, log=log)
+                   for sc in ("circle", "random") for t in (int(x) for x in args.teams.split(","))]
+            head = [r for r in res if r["scenario"] == "circle" and r["robots"] == 16] or res
+            out = {"metric": "mean wall time to the first conflict-free plan, 16 robots 2D holonomic, antipodal circle",
+                   "value": head[0]["mean_seconds_to_first_success"], "unit": "s", "n_gpus": 1,
+                   "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": "first_success", "description": "2D holonomic teams, antipodal circle and "
+                              "random targets in a square of the circle's diameter, T=100, M=2048, N=100, "
+                              "5 s deadline, 50 runs each"},
+                   "details": res}
         elif args.experiment == "sensitivity":
             res = E.sensitivity(L, dynamics=tuple(args.dynamics.split(",")),
                                 teams=tuple(int(t) for t in args.teams.split(",")), runs=args.runs,
-                                radius=args.radius, log=log)
+                                radius=args.radius or 2.0, log=log)
             mid = [c for c in res["cells"] if c["denoising_steps"] == 100]
             out = {"metric": "success rate within the iteration budget, mean over dynamics and team sizes at N=100",
                    "value": float(np.mean([c["success_within_iterations"][-1] for c in mid])), "unit": "fraction",
                    "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
                    "config": {"workload": "sensitivity", "description": f"antipodal circle (sphere in 3D) of radius "
-                              f"{args.radius} m, teams of {args.teams} robots, dynamics {args.dynamics}, T=100, M=2048, "
+                              f"{args.radius or 2.0} m, teams of {args.teams} robots, dynamics {args.dynamics}, T=100, M=2048, "
                               "N in {50, 100, 200, 300}, 5 iterations, independent runs per cell"},
                    "details": res}
         else:

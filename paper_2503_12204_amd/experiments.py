@@ -206,3 +206,59 @@ def sensitivity(L, dynamics=("diffdrive", "holo2d", "holo3d"), teams=(10, 16), s
                     + " ".join(f"{r:.2f}" for r in rate) + f"  ({secs * 1e3:.0f} ms per iteration of {runs} runs)")
     return {"runs_per_cell": runs, "samples": n_samples, "horizon": horizon, "iterations": iterations, "radius": radius,
             "denoising_steps": list(steps), "teams": list(teams), "dynamics": list(dynamics), "cells": cells}
+
+
+def first_success(L, scenario="circle", n=16, runs=50, n_samples=2048, horizon=100, n_steps=100, radius=4.0,
+                  deadline_s=5.0, max_iterations=500, seed=0, log=print):
+    """Wall time to the first conflict-free plan (Sec. V-C, the paper's
+    headline measure), single-problem path, 2D holonomic robots.
+
+    scenario "circle": n robots on an antipodal circle of the given radius,
+    run j drawing from its own Philox stream (instance id j).  "random":
+    start and goal sets drawn uniformly, at least 1 m apart, in a square whose
+    side is the circle's diameter (Sec. V-D), one instance per run.  The
+    clock covers the whole planning call, context set-up included, and stops
+    when an iteration returns a conflict-free plan or at the deadline."""
+    import math
+    rng = np.random.default_rng(seed)
+    p0, x00, g0 = W.holo2d_circle(n=n, horizon=horizon, n_samples=n_samples, n_steps=n_steps, radius=radius)
+    # untimed warm-up: library load, first graph capture
+    L.plan(p0, x00, g0, iterations=1)
+    torch.cuda.synchronize()
+    times, iters, solved = [], [], []
+    for j in range(runs):
+        if scenario == "circle":
+            p, x0, g = p0.replace(instance_id=j), x00, g0
+        else:
+            p, x0, g = W.random_instance(rng, W.HOLO2D, n, horizon, n_samples, box=2.0 * radius, min_sep=1.0,
+                                         n_steps=n_steps)
+            p = p.replace(instance_id=j)
+        t0 = time.perf_counter()
+        x0_d, g_d = L._f32(x0), L._f32(g)
+        u = torch.zeros((p.n_robots, p.horizon, p.du), dtype=torch.float32, device="cuda")
+        ctx = L.Context(p)
+        ok, k = False, 0
+        try:
+            while k < max_iterations and time.perf_counter() - t0 < deadline_s:
+                st = ctx.denoise_iter(x0_d, g_d, u, k)
+                k += 1
+                if st["success"]:
+                    ok = True
+                    break
+        finally:
+            ctx.close()
+        dt = time.perf_counter() - t0
+        solved.append(ok)
+        iters.append(k)
+        if ok:
+            times.append(dt)
+    solved = np.array(solved)
+    t = np.array(times) if times else np.array([math.nan])
+    log(f"{scenario} n={n}: solved {solved.mean():.2f} within {deadline_s} s, mean time to first success "
+        f"{t.mean() * 1e3:.1f} ms (median {np.median(t) * 1e3:.1f} ms), mean iterations {np.mean(iters):.2f}")
+    return {"scenario": scenario, "robots": n, "runs": runs, "samples": n_samples, "horizon": horizon,
+            "denoising_steps": n_steps, "radius_or_half_side": radius, "deadline_s": deadline_s,
+            "solved_fraction": float(solved.mean()), "mean_seconds_to_first_success": float(t.mean()),
+            "median_seconds_to_first_success": float(np.median(t)),
+            "mean_iterations": float(np.mean(iters)),
+            "iterations_of_solved_runs": [int(i) for i, s in zip(iters, solved) if s]}

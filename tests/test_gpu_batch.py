@@ -93,3 +93,16 @@ def test_sensitivity_sweep_cells(L):
     a, b = bc.plan_of(0).cpu().numpy(), bc.plan_of(1).cpu().numpy()
     bc.close()
     assert not np.array_equal(a, b)
+
+
+def test_first_success_experiment_runs(L):
+    """Time to the first conflict-free plan (the paper's headline measure):
+    tiny teams are solved at once on both scenarios, within the deadline."""
+    from paper_2503_12204_amd import experiments as E
+    for sc in ("circle", "random"):
+        print("first success", sc, "n=3 M=128 T=20 N=8, 2 runs", flush=True)
+        r = E.first_success(L, scenario=sc, n=3, runs=2, n_samples=128, horizon=20, n_steps=8, radius=4.0,
+                            deadline_s=5.0, max_iterations=20, log=lambda m: print(m, flush=True))
+        assert r["runs"] == 2 and 0.0 <= r["solved_fraction"] <= 1.0
+        assert len(r["iterations_of_solved_runs"]) == round(2 * r["solved_fraction"])
+        assert all(1 <= k <= 20 for k in r["iterations_of_solved_runs"])
