@@ -196,7 +196,7 @@ int32_t d4_denoise_iter(d4_ctx* ctx, const d4_problem* p, const float* x0, const
  * d4_fitness, d4_denoise_iter).  A tile is the number of samples per
  * workgroup S (1..64), the number of steps per LDS time block (a multiple of
  * 2 for d_u = 2, of 4 for d_u = 3) and the replica lanes R per (sample,
- * robot) (1..8; R > 1 lets R lanes share the draws and pair checks of one
+ * robot) (1..16; R > 1 lets R lanes share the draws and pair checks of one
  * lane, for problems with too few lanes to fill the GPU), with
  * S * n_robots <= 256 and R * S * n_robots <= 1024.  A tile changes only
  * speed: every admissible tile gives the same bits.  The batched form keeps

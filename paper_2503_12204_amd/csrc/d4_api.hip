@@ -504,7 +504,7 @@ int tile_ok(const d4_problem* p, Tile t) {
     // a workgroup holds S samples of all n robots (times R replicas): at most 256 lanes
     // for the one-lane kernel, 1024 for the cooperative one
     if (t.S < 1 || t.S > 64 || t.S * p->n_robots > 256) return fail(D4_EINVAL, "samples per group %d invalid", t.S);
-    if (t.R < 1 || t.R > 8 || t.R * t.S * p->n_robots > 1024) return fail(D4_EINVAL, "replicas %d invalid", t.R);
+    if (t.R < 1 || t.R > 16 || t.R * t.S * p->n_robots > 1024) return fail(D4_EINVAL, "replicas %d invalid", t.R);
     if (t.Tb < cs || t.Tb > 64 || t.Tb % cs) return fail(D4_EINVAL, "steps per block %d invalid", t.Tb);
     if (rollfit_lds(p, t) > LDS_DYNAMIC_MAX) return fail(D4_EUNSUPPORTED, "tile needs too much LDS");
     return D4_OK;
@@ -580,7 +580,7 @@ int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int
     float best = 1e30f;
     Tile best_t = default_tile(p->dyn, p->n_robots);
     const int cs = s.du == 2 ? 2 : 4;
-    for (int R : {1, 2, 4, 8}) for (int S : {4, 8, 16, 32, 64}) {
+    for (int R : {1, 2, 4, 8, 16}) for (int S : {4, 8, 16, 32, 64}) {
         for (int Tb : {2, 4, 8, 12, 16, 32}) {
             Tile t;
             t.S = S;

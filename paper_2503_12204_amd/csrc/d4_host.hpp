@@ -193,14 +193,14 @@ bool tile_override(int dyn, int n, int T, Tile* out);
 
 // Single-problem default: halve the samples per workgroup until there are at
 // least 256 workgroups (one per CU), then add replica lanes (cooperative
-// kernel), up to 8 and 512 lanes per workgroup, when a workgroup would be
+// kernel), up to 16 and 1024 lanes per workgroup, when a workgroup would be
 // smaller.
 inline Tile single_tile(int dyn, int n, int M) {
     Tile t = default_tile(dyn, n);
     int S = t.S;
     while (S > 1 && (M + S - 1) / S < 256) S >>= 1;
     if (S == t.S) return t;
-    const int R = std::max(1, std::min(8, 512 / (S * n)));
+    const int R = std::max(1, std::min(16, 1024 / (S * n)));
     const int cs = shape_of(dyn).du == 2 ? 2 : 4;
     const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
     const int Tb = R > 1 ? 16 : std::max(cs, std::min(16, ((32 * 1024) / (n * S * slot)) / cs * cs));
@@ -233,7 +233,7 @@ inline Tile pick_tile(const d4_problem* p) {
     const char* envr = std::getenv("D4_TILE_R");
     if (envr) {
         int v = std::atoi(envr);
-        if (v >= 1 && v <= 8) R = v;
+        if (v >= 1 && v <= 16) R = v;
     }
     if (R * S * n > 1024) R = std::max(1, 1024 / (S * n));
     Tile out;

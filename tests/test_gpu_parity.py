@@ -382,7 +382,7 @@ def test_cooperative_kernel_is_bit_identical(L, dyn, n, T, M, S, Tb):
     du = _cu((rng.normal(size=p.D) * 0.3).astype(np.float32))
     outs, plans = [], []
     try:
-        for R in (1, 2, 4, 8):
+        for R in (1, 2, 4, 8, 16):
             if R * S * n > 1024:
                 continue
             AT.set_tile(p.dyn, n, T, S, Tb, R)
@@ -434,7 +434,7 @@ def test_tile_does_not_change_results(L, dyn, n, T, M):
     p = p.replace(n_steps=5)
     u0 = _rand_controls(rng, p, 1, spread=0.5)[0]
     cs = 4 if p.du == 3 else 2
-    tiles = [(1, cs, 1), (3, 2 * cs, 1), (min(64, 256 // n), 4 * cs, 1), (2, 4 * cs, 2), (4, cs, 4), (1, 2 * cs, 8)]
+    tiles = [(1, cs, 1), (3, 2 * cs, 1), (min(64, 256 // n), 4 * cs, 1), (2, 4 * cs, 2), (4, cs, 4), (1, 2 * cs, 8), (1, cs, 16)]
     plans = []
     for S, Tb, R in tiles:
         if S * n > 256 or R * S * n > 1024:
