@@ -69,10 +69,11 @@ struct RollFitArgs {
 };
 
 // Stage a problem's obstacles in LDS (static, MAX_OBS slots); the caller
-// synchronises the workgroup before the first use.
+// synchronises the workgroup before the first use.  Workgroups can be
+// smaller than the obstacle count (a tile of one sample of two robots has two
+// lanes), so the lanes stride over the obstacles.
 __device__ __forceinline__ void stage_obstacles(const RollFitArgs& a, float4* obs_l) {
-    const int tid = threadIdx.x;
-    if (tid < a.n_obs) obs_l[tid] = a.obs ? a.obs[tid] : a.obs_inline[tid];
+    for (int o = threadIdx.x; o < a.n_obs; o += blockDim.x) obs_l[o] = a.obs ? a.obs[o] : a.obs_inline[o];
 }
 
 // Binary obstacle hit of a position: within the reward distance of any obstacle.

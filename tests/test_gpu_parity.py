@@ -488,3 +488,30 @@ def test_obstacles_are_avoided(L):
         out[name] = int(ofit.obstacle_hits(p, x, pred_dtype=np.float32).sum())
     assert out["without"] > 0
     assert out["with"] == 0
+
+
+def test_sixteen_obstacles_with_tiny_workgroups(L):
+    """Obstacle staging with workgroups smaller than the obstacle count (one
+    sample of two robots is two lanes): every tile sees all 16 obstacles, so
+    every tile gives the same plan and reward."""
+    from paper_2503_12204_amd import autotune as AT
+    rng = np.random.default_rng(16)
+    obs = tuple((0.4 + 0.75 * (i % 4), 0.4 + 0.75 * (i // 4), 0.0, 0.15) for i in range(16))
+    p, x0, g = W.random_instance(rng, W.HOLO2D, 2, 30, 64, box=3.0, min_sep=0.8, obstacles=obs)
+    p = p.replace(n_steps=5)
+    assert len(p.obstacles) == 16
+    plans = []
+    for S, Tb, R in [(32, 8, 1), (1, 2, 1), (2, 4, 1), (1, 2, 4)]:
+        AT.set_tile(p.dyn, p.n_robots, p.horizon, S, Tb, R)
+        try:
+            print("16 obstacles, tile", (S, Tb, R), flush=True)
+            ctx = L.Context(p)
+            u = torch.zeros((p.n_robots, p.horizon, p.du), dtype=torch.float32, device="cuda")
+            st = ctx.denoise_iter(_cu(x0), _cu(g), u, 0)
+            ctx.close()
+        finally:
+            AT.clear_tile(p.dyn, p.n_robots, p.horizon)
+        plans.append((S, Tb, R, _np(u), st["reward"], st["obstacle_hits"]))
+    for S, Tb, R, u, rew, oh in plans[1:]:
+        assert np.array_equal(u, plans[0][3]), f"tile {(S, Tb, R)}"
+        assert rew == plans[0][4] and oh == plans[0][5]
