@@ -574,8 +574,10 @@ int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int
         return fail(D4_ENOMEM, "autotune scratch allocation failed");
     }
     (void)hipMemset(ub, 0, 4 * D);
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        release();
+        return fail(D4_EHIP, "autotune could not create its timing events");
+    }
     const Schedule sc = make_schedule(p);
     float best = 1e30f;
     Tile best_t = default_tile(p->dyn, p->n_robots);
