@@ -62,12 +62,14 @@ HBM_PEAK_GBS = 8000.0
 #  - broad phase: (n - 1)/2 partners per robot and block of Tb steps, d_p fma
 #    + (3 d_p + 2) other each (differences, max, squares and sums, compare, or)
 #  - collision flags: 3 other
+#  - static obstacles: per obstacle and step, the squared distance and the
+#    compare: (d_p - 1) fma + (d_p + 3) other
 # The exact pair checks of partners the broad phase keeps are data dependent
 # and not counted.
 NORMAL_OPS = (11.0, 33.0, 1.0)
 
 
-def ops_per_unit(dyn, n, steps_per_block):
+def ops_per_unit(dyn, n, steps_per_block, n_obstacles=0):
     """Algorithmic (fma, other, transcendental) VALU operations per robot*step*sample."""
     from paper_2503_12204_amd import workloads as W
     dx, du, dp = W.dims(dyn)
@@ -76,6 +78,8 @@ def ops_per_unit(dyn, n, steps_per_block):
     fma = du * NORMAL_OPS[0] + 2 * du + dyn_ops[0] + dp + pairs * dp
     other = du * NORMAL_OPS[1] + 2 * du + dyn_ops[1] + (dp + 2) + 2 * dp + pairs * (3 * dp + 2) + 3
     trans = du * NORMAL_OPS[2] + dyn_ops[2] + 1
+    fma += n_obstacles * (dp - 1)
+    other += n_obstacles * (dp + 3)
     return fma, other, trans
 
 
@@ -89,6 +93,10 @@ WORKLOADS = {
     "holo3d_sphere_swap": "16 robots, 3D holonomic double integrator, antipodal sphere swap, T=100, M=8192, N=100",
     "unicycle_random": "8 unicycles, random starts/goals in a 10 m box, T=100, M=2048, N=100",
     "holo2d_circle_swap": "4 robots, 2D holonomic double integrator, antipodal circle swap, T=50, M=256, N=100",
+    "diffdrive_circle_swap": "16 robots, differential drive (x = [p, theta, v], u = [omega, a]), antipodal circle "
+                             "swap, T=100, M=8192, N=100",
+    "holo2d_circle_obstacles": "16 robots, 2D holonomic double integrator, antipodal circle swap around 4 static "
+                               "discs, T=100, M=8192, N=100",
 }
 
 
@@ -100,6 +108,10 @@ def make_workload(name):
         return W.unicycle_random()
     if name == "holo2d_circle_swap":
         return W.holo2d_circle()
+    if name == "diffdrive_circle_swap":
+        return W.diffdrive_circle(n=16, horizon=100, n_samples=8192)
+    if name == "holo2d_circle_obstacles":
+        return W.holo2d_circle_obstacles(n=16, n_obs=4, horizon=100, n_samples=8192)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -364,7 +376,7 @@ def main():
     t_k = time_fused_kernel_in_iteration(L, p, x0, g, u, args.warmup + args.steps + 1)
     from paper_2503_12204_amd import autotune as AT
     S_t, Tb_t, R_t = AT.get_tile(p)
-    opc = ops_per_unit(p.dyn, p.n_robots, Tb_t)
+    opc = ops_per_unit(p.dyn, p.n_robots, Tb_t, len(p.obstacles))
     opu = sum(opc)
     units = p.n_robots * p.horizon * p.n_samples
     achieved = opu * units / t_k
