@@ -127,17 +127,19 @@ def cpu_baseline(name, target_s=10.0):
     ms, sg, os_ = sched
     du = np.zeros(p.D)
     ub = np.zeros(p.D)
-    t0 = time.perf_counter()
+    from threadpoolctl import threadpool_limits
     steps = 0
     i = p.n_steps
-    while True:
-        out = ombd.sample_rewards(p, x0, g, ub, du, 0, i, sched=sched, samples=np.arange(S))
-        du, _ = ombd.mc_update(du, out["eps"], out["r"], ms[i], sg[i], os_[i], p.temperature, True)
-        steps += 1
-        i -= 1
-        if time.perf_counter() - t0 >= target_s or i == 0:
-            break
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):  # one core, whatever BLAS the oracle's NumPy would use
+        t0 = time.perf_counter()
+        while True:
+            out = ombd.sample_rewards(p, x0, g, ub, du, 0, i, sched=sched, samples=np.arange(S))
+            du, _ = ombd.mc_update(du, out["eps"], out["r"], ms[i], sg[i], os_[i], p.temperature, True)
+            steps += 1
+            i -= 1
+            if time.perf_counter() - t0 >= target_s or i == 0:
+                break
+        dt = time.perf_counter() - t0
     units = p.n_robots * p.horizon * S * steps
     return {"value": units / dt, "unit": "robot*step*samples/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} denoising steps of {name} restricted to samples 0..{S - 1} "
