@@ -118,7 +118,8 @@ enum { MODE_FUSED = 1, MODE_FROM_X = 2, MODE_FUSED_ALIGNED = 3 };
 // Collision bits of robot k at one step: bit l set when partner l = k + j
 // (mod n), j = 1..jmax, is within the reward threshold.  pb points at slot 0
 // of this sample's step; the step holds 2n - 1 slots (robots 0..n-1, then
-// 0..n-2 again, S apart), so the partners are contiguous.  Hits are collected
+// 0..n-2 again, S apart: the cooperative kernel's layout), so the partners
+// are contiguous.  Hits are collected
 // at unwrapped positions k + j < 2n and folded back modulo n.
 template <int DP>
 __device__ __forceinline__ uint32_t pair_bits(const typename PosSlot<DP>::T* pb, int n, int S, int k, int jmax,
