@@ -191,10 +191,23 @@ inline Tile default_tile(int dyn, int n) {
 // Tuned tile of a problem shape installed by d4_tile_set / d4_autotune, if any.
 bool tile_override(int dyn, int n, int T, Tile* out);
 
+// Dynamic LDS of the cooperative kernel: controls [n][G][4][S] (G = Tb d_u / 4
+// + 1 Philox blocks per robot and time block), single-buffered positions
+// [Tb][2n-1][S] and masks [2][Tb][S]; the final reductions reuse the space.
+inline size_t coop_lds(int dyn, size_t n, size_t S, size_t Tb, size_t R) {
+    const Shape s = shape_of(dyn);
+    const size_t slot = s.dp == 3 ? 16 : 8;
+    const size_t G = Tb * s.du / 4 + 1;
+    const size_t a = n * G * 4 * S * 4 + Tb * (2 * n - 1) * S * slot + 2 * Tb * S * 4;
+    const size_t b = (3 + R) * n * S * 4;
+    return a > b ? a : b;
+}
+
 // Single-problem default: halve the samples per workgroup until there are at
 // least 256 workgroups (one per CU), then add replica lanes (cooperative
 // kernel), up to 16 and 1024 lanes per workgroup, when a workgroup would be
-// smaller.
+// smaller.  The cooperative kernel's rollout runs on one replica between
+// barriers, so its time blocks are as long as the LDS allows (up to 64 steps).
 inline Tile single_tile(int dyn, int n, int M) {
     Tile t = default_tile(dyn, n);
     int S = t.S;
@@ -203,7 +216,11 @@ inline Tile single_tile(int dyn, int n, int M) {
     const int R = std::max(1, std::min(16, 1024 / (S * n)));
     const int cs = shape_of(dyn).du == 2 ? 2 : 4;
     const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
-    const int Tb = R > 1 ? 16 : std::max(cs, std::min(16, ((32 * 1024) / (n * S * slot)) / cs * cs));
+    int Tb = std::max(cs, std::min(16, ((32 * 1024) / (n * S * slot)) / cs * cs));
+    if (R > 1) {
+        Tb = 64;
+        while (Tb > cs && coop_lds(dyn, n, S, Tb, R) > LDS_DYNAMIC_MAX) Tb -= cs;
+    }
     Tile out;
     out.S = S;
     out.Tb = Tb;
@@ -247,13 +264,7 @@ inline size_t rollfit_lds(const d4_problem* p, Tile t) {
     const Shape s = shape_of(p->dyn);
     const size_t n = p->n_robots;
     const size_t slot = s.dp == 3 ? 16 : 8;
-    const size_t n2 = 2 * n - 1;  // position slots per step
-    if (t.R > 1) {  // cooperative kernel: draws, single-buffered positions, masks
-        const size_t G = (size_t)t.Tb * s.du / 4 + 1;
-        const size_t a = n * G * 4 * t.S * 4 + (size_t)t.Tb * n2 * t.S * slot + (size_t)2 * t.Tb * t.S * 4;
-        const size_t b = (size_t)(3 + t.R) * n * t.S * 4;
-        return a > b ? a : b;
-    }
+    if (t.R > 1) return coop_lds(p->dyn, n, t.S, t.Tb, t.R);
     // one-lane kernel: positions [Tb][n][S], boxes [n][S][2], masks [2][Tb][S], flags [2][S]
     const size_t a = (size_t)t.Tb * n * t.S * slot + (size_t)2 * n * t.S * slot +
                      (size_t)2 * t.Tb * t.S * 4 + (size_t)2 * t.S * 4;

@@ -447,12 +447,13 @@ __global__ void __launch_bounds__(256) k_rollfit(const RollFitArgs a) {
 // Cooperative variant of the fused kernel for problems with few (sample,
 // robot) lanes: R replica lanes per (sample, robot).  Per time block of Tb
 // steps: (1) all replicas generate the robot's draws of the block, whole
-// Philox blocks, into LDS (and eps); (2) replica 0 rolls the robot out over
-// the block, reading its draws from LDS; (3) all replicas share the pair
+// Philox blocks, write them to eps and turn them into the block's sampled
+// controls in LDS; (2) replica 0 rolls the robot out over the block, reading
+// its controls from LDS; (3) all replicas share the pair
 // checks, step tt going to replica tt mod R; (4) replica 0 reads the collision
 // masks.  Every value is computed as in the one-lane kernel and every sum is
 // taken in the same order, so the results are identical to it.
-// Lanes: tid = rep * (n*S) + k * S + ms.  LDS: draws [n][G][4][S] floats with
+// Lanes: tid = rep * (n*S) + k * S + ms.  LDS: controls [n][G][4][S] floats with
 // G = Tb*d_u/4 + 1, positions [Tb][2n-1][S] slots, masks [2][Tb][S].
 template <int DYN, int MODE>
 __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, int m0, float* lds) {
@@ -517,32 +518,43 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
         const uint32_t e_hi = e_lo + (uint32_t)(tcount * DU);
         const uint32_t g_a = e_lo >> 2;
         const int G_b = (int)(((e_hi - 1) >> 2) - g_a) + 1;
-        // (1) draws of this block
+        // (1) draws of this block, and from them the block's sampled controls:
+        // the replicas read the control bases in parallel, so the rollout's
+        // serial step chain holds no global load (LDS keeps u; eps gets z)
         if (active) {
             for (int gi = rep; gi < G_b; gi += R) {
                 float z[4];
                 normal_block(g_a + (uint32_t)gi, (uint32_t)mc, c2, a.inst, a.key0, a.key1, z[0], z[1], z[2], z[3]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    nzk[(size_t)(gi * 4 + j) * S] = z[j];
                     const uint32_t e = 4 * (g_a + (uint32_t)gi) + (uint32_t)j;
-                    if (live && e >= e_lo && e < e_hi) a.eps[(size_t)e * Ms + m] = z[j];
+                    const bool in_blk = e >= e_lo && e < e_hi;
+                    float v = z[j];
+                    if (in_blk) {
+                        const int d = (int)((e - ebase) % (uint32_t)DU);
+                        const float lo = d == 0 ? ulo[0] : d == 1 ? ulo[DU > 1 ? 1 : 0] : ulo[DU - 1];
+                        const float hi = d == 0 ? uhi[0] : d == 1 ? uhi[DU > 1 ? 1 : 0] : uhi[DU - 1];
+                        v = sample_control(a.u_base[e], a.du_in[e], mscale, sigma, z[j], lo, hi);
+                    }
+                    nzk[(size_t)(gi * 4 + j) * S] = v;
+                    if (live && in_blk) a.eps[(size_t)e * Ms + m] = z[j];
                 }
             }
         }
         if (rep == 0 && k == 0 && active)
             for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
         __syncthreads();
-        // (2) rollout of the block by replica 0
+        // (2) rollout of the block by replica 0 (unrolled, so that the next
+        // steps' control reads run ahead of the state chain)
         if (rep == 0 && active) {
+#pragma unroll 4
             for (int tt = 0; tt < tcount; ++tt) {
                 const int t = t0 + tt;
                 float u[DU];
 #pragma unroll
                 for (int d = 0; d < DU; ++d) {
                     const uint32_t e = ebase + (uint32_t)(t * DU + d);
-                    const float z = nzk[(size_t)(((e >> 2) - g_a) * 4 + (e & 3u)) * S];
-                    u[d] = sample_control(a.u_base[e], a.du_in[e], mscale, sigma, z, ulo[d], uhi[d]);
+                    u[d] = nzk[(size_t)(((e >> 2) - g_a) * 4 + (e & 3u)) * S];
                 }
                 DY::step(x, aux, u, a.sc);
                 goal_acc += goal_term(fast_sqrt(goal_d2<DP>(x, g)), inv_d0);
