@@ -24,23 +24,67 @@ enum { HOLO2D = 0, HOLO3D = 1, UNICYCLE = 2, DIFFDRIVE = 3 };
 constexpr int MAX_OBS = 16;   // static obstacles per problem
 enum { FLAG_NORMALIZE = 1, FLAG_SAFE_PAIRS = 2 };
 
+// ---------------------------------------------------- uniform values in VGPRs
+// A VALU instruction that reads an SGPR operand issues in 4 cycles on gfx950,
+// but one whose sources are all VGPRs (or inline constants) can pair with
+// another wave's instruction and issue in about 2.5 (a probe of ours: FP32
+// add and multiply, 4.4 against 2.45 cycles per wave64).  The hot loops
+// therefore take their uniform operands from VGPR copies.  The empty asm
+// ties the value to a VGPR and hides its origin, so the optimiser neither
+// folds it back to the scalar register nor rematerialises it there.
+__device__ __forceinline__ float vgpr_copy(float x) {
+    float r;
+    asm volatile("" : "=v"(r) : "0"(x));
+    return r;
+}
+__device__ __forceinline__ uint32_t vgpr_copy(uint32_t x) {
+    uint32_t r;
+    asm volatile("" : "=v"(r) : "0"(x));
+    return r;
+}
+
 // ------------------------------------------------------------------ Philox
+// The constants of Philox4x32-10 under one key: the two round multipliers
+// and the ten round keys (the key advanced by the Weyl constants), in VGPRs
+// when IN_VGPRS.
+struct PhiloxKey {
+    uint32_t m0, m1, k0[10], k1[10];
+    template <bool IN_VGPRS>
+    __device__ __forceinline__ static PhiloxKey make(uint32_t key0, uint32_t key1) {
+        PhiloxKey pk;
+        pk.m0 = 0xD2511F53u;
+        pk.m1 = 0xCD9E8D57u;
+#pragma unroll
+        for (int r = 0; r < 10; ++r) {
+            pk.k0[r] = key0 + (uint32_t)r * 0x9E3779B9u;
+            pk.k1[r] = key1 + (uint32_t)r * 0xBB67AE85u;
+        }
+        if (IN_VGPRS) {
+            pk.m0 = vgpr_copy(pk.m0);
+            pk.m1 = vgpr_copy(pk.m1);
+#pragma unroll
+            for (int r = 0; r < 10; ++r) {
+                pk.k0[r] = vgpr_copy(pk.k0[r]);
+                pk.k1[r] = vgpr_copy(pk.k1[r]);
+            }
+        }
+        return pk;
+    }
+};
+
 // Philox4x32-10 on G independent counter blocks under one key.  The rounds
 // run in lockstep across the blocks: each round is a short dependent chain
 // (two 32x32->64 products feeding two three-input XORs), so interleaving
 // the blocks keeps 2G products in flight instead of two.
 template <int G>
-__device__ __forceinline__ void philox4x32_10_n(uint32_t (&c)[G][4], uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ void philox4x32_10_n(uint32_t (&c)[G][4], const PhiloxKey& pk) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
+        const uint32_t k0 = pk.k0[r], k1 = pk.k1[r];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            const uint64_t p0 = (uint64_t)0xD2511F53u * c[q][0];
-            const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[q][2];
+            const uint64_t p0 = (uint64_t)pk.m0 * c[q][0];
+            const uint64_t p1 = (uint64_t)pk.m1 * c[q][2];
             const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
             const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
             // three-input XORs (truth table 0x96) in one gfx950 instruction each
@@ -57,7 +101,7 @@ __device__ __forceinline__ void philox4x32_10_n(uint32_t (&c)[G][4], uint32_t k0
 __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
                                               uint32_t& c3, uint32_t k0, uint32_t k1) {
     uint32_t c[1][4] = {{c0, c1, c2, c3}};
-    philox4x32_10_n<1>(c, k0, k1);
+    philox4x32_10_n<1>(c, PhiloxKey::make<false>(k0, k1));
     c0 = c[0][0];
     c1 = c[0][1];
     c2 = c[0][2];
@@ -230,19 +274,21 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z_ev
 }
 
 // The 4G normals of the consecutive Philox blocks group0 .. group0+G-1 of
-// sample m, block q's four normals at z[4q .. 4q+3].
-template <int G>
+// sample m, block q's four normals at z[4q .. 4q+3].  c2 and c3 (uniform)
+// enter the first round's product and XOR, so they go in as VGPR copies too
+// when the key does.
+template <int G, bool IN_VGPRS>
 __device__ __forceinline__ void normal_blocks(uint32_t group0, uint32_t m, uint32_t c2, uint32_t c3,
-                                              uint32_t k0, uint32_t k1, float* z) {
+                                              const PhiloxKey& pk, float* z) {
     uint32_t w[G][4];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         w[q][0] = group0 + (uint32_t)q;
         w[q][1] = m;
-        w[q][2] = c2;
-        w[q][3] = c3;
+        w[q][2] = IN_VGPRS ? vgpr_copy(c2) : c2;
+        w[q][3] = IN_VGPRS ? vgpr_copy(c3) : c3;
     }
-    philox4x32_10_n<G>(w, k0, k1);
+    philox4x32_10_n<G>(w, pk);
     uint32_t wa[2 * G], wb[2 * G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -265,7 +311,7 @@ __device__ __forceinline__ void normal_block(uint32_t group, uint32_t m, uint32_
                                              uint32_t k0, uint32_t k1, float& z0, float& z1,
                                              float& z2, float& z3) {
     float z[4];
-    normal_blocks<1>(group, m, c2, c3, k0, k1, z);
+    normal_blocks<1, false>(group, m, c2, c3, PhiloxKey::make<false>(k0, k1), z);
     z0 = z[0];
     z1 = z[1];
     z2 = z[2];
@@ -279,14 +325,14 @@ __device__ __forceinline__ float clamp_f(float x, float lo, float hi) {
     return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
 // Running min and max of finite values as medians with -inf and +inf (no
-// operand quieting, unlike fminf/fmaxf).  The infinities come from scalar
-// register moves the optimiser cannot see through, which keeps it from
-// folding the medians back into minnum/maxnum.
+// operand quieting, unlike fminf/fmaxf).  The infinities are VGPR copies the
+// optimiser cannot see through, which keeps it from folding the medians back
+// into minnum/maxnum (and keeps SGPR operands out of the medians).
 struct MinMaxInf {
     float ninf, pinf;
     __device__ __forceinline__ MinMaxInf() {
-        asm volatile("s_mov_b32 %0, 0xff800000" : "=s"(ninf));
-        asm volatile("s_mov_b32 %0, 0x7f800000" : "=s"(pinf));
+        ninf = vgpr_copy(-INFINITY);
+        pinf = vgpr_copy(INFINITY);
     }
     __device__ __forceinline__ float min(float a, float b) const { return __builtin_amdgcn_fmed3f(a, b, ninf); }
     __device__ __forceinline__ float max(float a, float b) const { return __builtin_amdgcn_fmed3f(a, b, pinf); }

@@ -246,7 +246,21 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
         ulo[d] = a.ulo[d];
         uhi[d] = a.uhi[d];
     }
-    const float sigma = a.sigma, mscale = a.mean_scale;
+    // the draw, sampling and dynamics loop reads its uniform operands from
+    // VGPR copies (an SGPR operand keeps a VALU instruction from pairing)
+    const float sigma = vgpr_copy(a.sigma), mscale = vgpr_copy(a.mean_scale);
+#pragma unroll
+    for (int d = 0; d < DU; ++d) {
+        ulo[d] = vgpr_copy(ulo[d]);
+        uhi[d] = vgpr_copy(uhi[d]);
+    }
+    StepConsts sc = a.sc;
+    sc.dt = vgpr_copy(sc.dt);
+    sc.hdt = vgpr_copy(sc.hdt);
+    sc.hdt2 = vgpr_copy(sc.hdt2);
+    sc.dt6 = vgpr_copy(sc.dt6);
+    sc.vmax = vgpr_copy(sc.vmax);
+    const PhiloxKey pk = PhiloxKey::make<true>(a.key0, a.key1);
     const int jmax = active ? ((n - 1) >> 1) + ((((n & 1) == 0) && (k < (n >> 1))) ? 1 : 0) : 0;
     const bool pairs_mode = (a.flags & FLAG_SAFE_PAIRS) != 0;
     const size_t Ms = (size_t)M;
@@ -322,7 +336,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                 float win[4 + 4 * CG];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) win[j] = left[j];
-                normal_blocks<CG>(g0 + 1, (uint32_t)mc, c2, a.inst, a.key0, a.key1, win + 4);
+                normal_blocks<CG, true>(g0 + 1, (uint32_t)mc, c2, a.inst, pk, win + 4);
                 float z[4 * CG];
 #pragma unroll
                 for (int j = 0; j < 4 * CG; ++j)
@@ -356,7 +370,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                         for (int d = 0; d < DU; ++d) {
                             u[d] = sample_from_mean(mean_c[s * DU + d], sigma, z[s * DU + d], ulo[d], uhi[d]);
                         }
-                        DY::step(x, aux, u, a.sc);
+                        DY::step(x, aux, u, sc);
                         after_step(tc + s);
                     }
                 }
