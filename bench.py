@@ -11,7 +11,8 @@ The JSON line also carries:
   roofline      the fused sample+rollout+reward kernel (the dominant kernel):
                 algorithmic VALU operations per launch over its average
                 launch time, measured with HIP events on its stream, against
-                the VALU issue peak of 256 CUs x 64 lanes x 2.4 GHz.
+                the VALU issue peak of that operation mix on 256 CUs x 4
+                SIMDs at 2.4 GHz (full, half and quarter rate classes).
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -28,65 +29,74 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# gfx950 VALU issue rates (256 CUs x 4 SIMDs at 2.4 GHz), lanes per second:
-# a fused multiply-add issues a wave64 in 2 cycles (the 157.3 TFLOP/s FP32
-# vector figure: 32 FMA lanes per SIMD and cycle); other VALU instructions
-# (add, multiply, min/max, compares, selects, integer and logic, conversions,
-# the 32x32->64 product) in 4; transcendentals (reciprocal, square root) in 8.
+# gfx950 VALU issue classes (256 CUs x 4 SIMDs at 2.4 GHz), lanes per second.
+# The 157.3 TFLOP/s FP32 vector figure is 32 lanes per SIMD and cycle: a
+# wave64 instruction in 2 cycles.  That full rate holds for FP32 add,
+# subtract, multiply and fused multiply-add, and for 32-bit integer add,
+# subtract, logic (three-input bitop3 included), shifts and moves, when every
+# operand is a VGPR, an inline constant or a literal.  Compares, selects,
+# min/max/median, conversions, 32-bit multiplies and the 32x32->64 product,
+# three-operand integer forms (add3, shift-add, and-or), bit-field extracts
+# and any instruction with a scalar-register operand issue at half that rate
+# (4 cycles); transcendentals (reciprocal, square root, exp, sin) at a quarter
+# (8 cycles).  A throughput probe of 16 independent chains per lane, one
+# instruction form at a time, measures 2.3-2.9, 4.1-4.8 and 8.1-8.5 cycles.
 SIMD_HZ = 256 * 4 * 2.4e9
-FMA_RATE = SIMD_HZ * 32
-OTHER_RATE = SIMD_HZ * 16
-TRANS_RATE = SIMD_HZ * 8
+FULL_RATE = SIMD_HZ * 32
+HALF_RATE = SIMD_HZ * 16
+QUARTER_RATE = SIMD_HZ * 8
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic VALU operations per robot*step*sample of the fused kernel: the
 # operations each step of the method needs in its leanest gfx950 form (one
-# VALU instruction per arithmetic step, a fused multiply-add or a 32x32->64
-# product counted once), independent of how the kernel schedules them, split
-# into (fma, other, transcendental):
-#  - standard normal: Philox4x32-10 = 10 rounds of two 32x32->64 products and
-#    two three-input XORs, plus the counter set-up: 50 other per block of 4
-#    normals; Box-Muller per pair: uniform 3 other; ln 12 fma + 12 other +
-#    1 reciprocal (of which the division 6 fma + 1 other + 1 reciprocal);
-#    -2 ln 1 other; corrected square root 2 fma + 4 other + 1 square root;
-#    sin/cos with the quadrant rotation 8 fma + 19 other; two products 2 other.
-#    Per normal: 11 fma + 33 other + 1 transcendental.
-#  - sampled control: fma, fma, max, min per component
-#  - dynamics per step: double integrator 3 fma + 2 other (clip) per axis;
-#    unicycle 6 fma + 3 other + 4 transcendental (two heading updates, the
-#    mid-step and end-of-step sin/cos, Simpson sums); differential drive
-#    8 fma + 5 other + 4 transcendental (the speed's two steps and its clip)
-#  - goal term: squared distance d_p fma-or-product steps, square root, fused
-#    step, sum: d_p fma + (d_p + 2) other + 1 transcendental
-#  - bounding box of the block: 2 d_p other
-#  - broad phase: (n - 1)/2 partners per robot and block of Tb steps, d_p fma
-#    + (3 d_p + 2) other each (differences, max, squares and sums, compare, or)
-#  - collision flags: 3 other
-#  - static obstacles: per obstacle and step, the squared distance and the
-#    compare: (d_p - 1) fma + (d_p + 3) other
+# VALU instruction per arithmetic step, a fused multiply-add, a clamp as one
+# median, a 32x32->64 product counted once), independent of how the kernel
+# schedules them, split into the (full, half, quarter) rate classes above:
+#  - standard normal, per block of 4: Philox4x32-10 = 10 rounds of two
+#    32x32->64 products (half) and two three-input XORs (full), and 2 full for
+#    the counter; per Box-Muller pair: uniform 3 full + 1 half (conversion);
+#    ln: range reduction 4 full + 5 half, division 8 full + 1 reciprocal,
+#    series and e*ln2 9 full; -2 ln 1 full; corrected square root 4 full +
+#    4 half + 1 square root; sin/cos with the quarter-turn rotation 22 full +
+#    4 half; two products 2 full.  Per normal: 32 full + 12 half + 1 quarter.
+#  - sampled control: two fused multiply-adds and a clamp per component
+#  - dynamics per step: double integrator 3 full + 1 half (speed clamp) per
+#    axis; unicycle 11 full + 4 quarter (two heading updates, the mid-step and
+#    end-of-step sin/cos with their range scaling, Simpson sums); differential
+#    drive 17 full + 1 half + 4 quarter (the speed's two steps, its clamp)
+#  - goal term: differences, squared distance, square root, fused step, sum:
+#    2 d_p + 2 full + 1 quarter
+#  - bounding box of the block: running min and max, 2 d_p half
+#  - broad phase: (n - 1)/2 partners per robot and block of Tb steps; per
+#    partner the box gap (2 differences full and a three-way max half per
+#    axis), squares and sums d_p full, compare half, or full:
+#    3 d_p + 1 full + d_p + 1 half
+#  - collision flags: 3 full
+#  - static obstacles: per obstacle and step, differences, squared distance,
+#    or full and the compare half: 2 d_p + 1 full + 1 half
 # The exact pair checks of partners the broad phase keeps are data dependent
 # and not counted.
-NORMAL_OPS = (11.0, 33.0, 1.0)
+NORMAL_OPS = (32.0, 12.0, 1.0)
 
 
 def ops_per_unit(dyn, n, steps_per_block, n_obstacles=0):
-    """Algorithmic (fma, other, transcendental) VALU operations per robot*step*sample."""
+    """Algorithmic (full, half, quarter rate) VALU operations per robot*step*sample."""
     from paper_2503_12204_amd import workloads as W
     dx, du, dp = W.dims(dyn)
-    dyn_ops = {W.UNICYCLE: (6, 3, 4), W.DIFFDRIVE: (8, 5, 4)}.get(dyn, (3 * dp, 2 * dp, 0))
+    dyn_ops = {W.UNICYCLE: (11, 0, 4), W.DIFFDRIVE: (17, 1, 4)}.get(dyn, (3 * dp, dp, 0))
     pairs = (n - 1) / 2.0 / steps_per_block
-    fma = du * NORMAL_OPS[0] + 2 * du + dyn_ops[0] + dp + pairs * dp
-    other = du * NORMAL_OPS[1] + 2 * du + dyn_ops[1] + (dp + 2) + 2 * dp + pairs * (3 * dp + 2) + 3
-    trans = du * NORMAL_OPS[2] + dyn_ops[2] + 1
-    fma += n_obstacles * (dp - 1)
-    other += n_obstacles * (dp + 3)
-    return fma, other, trans
+    full = du * NORMAL_OPS[0] + 2 * du + dyn_ops[0] + (2 * dp + 2) + pairs * (3 * dp + 1) + 3
+    half = du * NORMAL_OPS[1] + du + dyn_ops[1] + 2 * dp + pairs * (dp + 1)
+    quarter = du * NORMAL_OPS[2] + dyn_ops[2] + 1
+    full += n_obstacles * (2 * dp + 1)
+    half += n_obstacles * 1
+    return full, half, quarter
 
 
 def issue_seconds_per_unit(ops):
     """Ideal VALU time of one robot*step*sample at the issue rates above."""
-    fma, other, trans = ops
-    return fma / FMA_RATE + other / OTHER_RATE + trans / TRANS_RATE
+    full, half, quarter = ops
+    return full / FULL_RATE + half / HALF_RATE + quarter / QUARTER_RATE
 
 
 WORKLOADS = {
@@ -387,7 +397,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": "T lane-ops/s", "frac": achieved / peak, "traffic": stored_traffic(args.workload),
                 "kernel": "k_rollfit (fused sample+rollout+reward)", "kernel_us": t_k * 1e6,
-                "ops_per_unit": opu, "ops_per_unit_fma_other_trans": list(opc),
+                "ops_per_unit": opu, "ops_per_unit_full_half_quarter": list(opc),
                 "tile": {"samples_per_group": S_t, "steps_per_block": Tb_t,
                                               "replicas": R_t}}
     # the weighted reduction: HBM-bound; algorithmic bytes = the draws read
