@@ -153,28 +153,8 @@ __device__ __forceinline__ uint32_t pair_bits(const typename PosSlot<DP>::T* pb,
     return (uint32_t)((bits | (bits >> n)) & low);
 }
 
-// Hit bits of robot k at one step against the partners j (bit j of near)
-// that the block's bounding boxes could not rule out; the remaining partners
-// hold no hit in this block.  Positions are stored once per robot ([n][S] per
-// step): partner j of robot k is robot (k + 1 + j) mod n, and a hit sets its bit.
-template <int DP>
-__device__ __forceinline__ uint32_t pair_bits_near_wrap(const typename PosSlot<DP>::T* pb, int n, int S, int k,
-                                                        uint32_t near, float thr2) {
-    using PS = PosSlot<DP>;
-    float pk[DP];
-    PS::unpack(pb[k * S], pk);
-    uint32_t bits = 0u;
-    while (near) {
-        const int j = __builtin_ctz(near);
-        near &= near - 1u;
-        int l = k + 1 + j;
-        l = l >= n ? l - n : l;
-        float pl[DP];
-        PS::unpack(pb[l * S], pl);
-        if (pair_d2<DP>(pk, pl) <= thr2) bits |= 1u << l;
-    }
-    return bits;
-}
+// Steps of a time block whose narrow-phase checks are read from LDS together.
+constexpr int NARROW_STEPS = 4;
 
 // Steps per noise chunk (a whole number of Philox blocks) and blocks per chunk.
 template <int DU>
@@ -405,15 +385,42 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                 l = l + 1 < n ? l + 1 : 0;
             }
         }
-        // narrow phase: exact checks of those partners at every step of the block
+        // narrow phase: exact checks of those partners at every step of the
+        // block, four steps at a time, so that the LDS reads of the four steps
+        // are in flight together (the mask updates come after the reads)
         if (near) {
             bool any = false;
-            for (int tt = 0; tt < tcount; ++tt) {
-                const uint32_t bits = pair_bits_near_wrap<DP>(pos + tt * n * S + ms, n, S, k, near, a.thr2);
-                hit_cnt += __popc(bits);
-                if (bits) {
-                    atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));
-                    any = true;
+            for (int tt0 = 0; tt0 < tcount; tt0 += NARROW_STEPS) {
+                float pk[NARROW_STEPS][DP];
+#pragma unroll
+                for (int q = 0; q < NARROW_STEPS; ++q) {
+                    const int tt = tt0 + q < tcount ? tt0 + q : tcount - 1;
+                    PS::unpack(pos[(tt * n + k) * S + ms], pk[q]);
+                }
+                uint32_t bits[NARROW_STEPS];
+#pragma unroll
+                for (int q = 0; q < NARROW_STEPS; ++q) bits[q] = 0u;
+                uint32_t nb = near;
+                while (nb) {
+                    const int j = __builtin_ctz(nb);
+                    nb &= nb - 1u;
+                    int l = k + 1 + j;
+                    l = l >= n ? l - n : l;
+#pragma unroll
+                    for (int q = 0; q < NARROW_STEPS; ++q) {
+                        const int tt = tt0 + q < tcount ? tt0 + q : tcount - 1;
+                        float pl[DP];
+                        PS::unpack(pos[(tt * n + l) * S + ms], pl);
+                        bits[q] |= (pair_d2<DP>(pk[q], pl) <= a.thr2) ? (1u << l) : 0u;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < NARROW_STEPS; ++q) {
+                    if (tt0 + q < tcount && bits[q]) {
+                        hit_cnt += __popc(bits[q]);
+                        atomicOr(&mask[(buf * Tb + tt0 + q) * S + ms], bits[q] | (1u << k));
+                        any = true;
+                    }
                 }
             }
             if (any) atomicOr(&anyhit[buf * S + ms], 1u);
