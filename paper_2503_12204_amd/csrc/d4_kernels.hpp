@@ -153,7 +153,9 @@ __device__ __forceinline__ uint32_t pair_bits(const typename PosSlot<DP>::T* pb,
     return (uint32_t)((bits | (bits >> n)) & low);
 }
 
-// Steps of a time block whose narrow-phase checks are read from LDS together.
+// Steps of a time block whose narrow-phase checks are read from LDS together
+// (the batched kernel, which holds every model's code, takes one at a time:
+// the unrolled form grows each copy and slowed a mixed batch by 14 %).
 constexpr int NARROW_STEPS = 4;
 
 // Steps per noise chunk (a whole number of Philox blocks) and blocks per chunk.
@@ -168,7 +170,7 @@ struct Chunk {
 // Chunk::STEPS.  MODE_FROM_X reads trajectories instead.
 // One tile: samples m0 .. m0+S-1 of one problem, lanes tid < n*S (the rest of
 // the workgroup idles through the barriers).
-template <int DYN, int MODE>
+template <int DYN, int MODE, int NS = NARROW_STEPS>
 __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float* lds) {
     using DY = Dyn<DYN>;
     constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
@@ -390,16 +392,16 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
         // are in flight together (the mask updates come after the reads)
         if (near) {
             bool any = false;
-            for (int tt0 = 0; tt0 < tcount; tt0 += NARROW_STEPS) {
-                float pk[NARROW_STEPS][DP];
+            for (int tt0 = 0; tt0 < tcount; tt0 += NS) {
+                float pk[NS][DP];
 #pragma unroll
-                for (int q = 0; q < NARROW_STEPS; ++q) {
+                for (int q = 0; q < NS; ++q) {
                     const int tt = tt0 + q < tcount ? tt0 + q : tcount - 1;
                     PS::unpack(pos[(tt * n + k) * S + ms], pk[q]);
                 }
-                uint32_t bits[NARROW_STEPS];
+                uint32_t bits[NS];
 #pragma unroll
-                for (int q = 0; q < NARROW_STEPS; ++q) bits[q] = 0u;
+                for (int q = 0; q < NS; ++q) bits[q] = 0u;
                 uint32_t nb = near;
                 while (nb) {
                     const int j = __builtin_ctz(nb);
@@ -407,7 +409,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                     int l = k + 1 + j;
                     l = l >= n ? l - n : l;
 #pragma unroll
-                    for (int q = 0; q < NARROW_STEPS; ++q) {
+                    for (int q = 0; q < NS; ++q) {
                         const int tt = tt0 + q < tcount ? tt0 + q : tcount - 1;
                         float pl[DP];
                         PS::unpack(pos[(tt * n + l) * S + ms], pl);
@@ -415,7 +417,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < NARROW_STEPS; ++q) {
+                for (int q = 0; q < NS; ++q) {
                     if (tt0 + q < tcount && bits[q]) {
                         hit_cnt += __popc(bits[q]);
                         atomicOr(&mask[(buf * Tb + tt0 + q) * S + ms], bits[q] | (1u << k));
@@ -1169,20 +1171,20 @@ static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArg
     const bool al = in.mode == MODE_FUSED_ALIGNED;
     switch (in.dyn) {
         case HOLO2D:
-            if (al) rollfit_tile<HOLO2D, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
-            else rollfit_tile<HOLO2D, MODE_FUSED>(a, tl.m0, lds);
+            if (al) rollfit_tile<HOLO2D, MODE_FUSED_ALIGNED, 1>(a, tl.m0, lds);
+            else rollfit_tile<HOLO2D, MODE_FUSED, 1>(a, tl.m0, lds);
             break;
         case HOLO3D:
-            if (al) rollfit_tile<HOLO3D, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
-            else rollfit_tile<HOLO3D, MODE_FUSED>(a, tl.m0, lds);
+            if (al) rollfit_tile<HOLO3D, MODE_FUSED_ALIGNED, 1>(a, tl.m0, lds);
+            else rollfit_tile<HOLO3D, MODE_FUSED, 1>(a, tl.m0, lds);
             break;
         case UNICYCLE:
-            if (al) rollfit_tile<UNICYCLE, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
-            else rollfit_tile<UNICYCLE, MODE_FUSED>(a, tl.m0, lds);
+            if (al) rollfit_tile<UNICYCLE, MODE_FUSED_ALIGNED, 1>(a, tl.m0, lds);
+            else rollfit_tile<UNICYCLE, MODE_FUSED, 1>(a, tl.m0, lds);
             break;
         default:
-            if (al) rollfit_tile<DIFFDRIVE, MODE_FUSED_ALIGNED>(a, tl.m0, lds);
-            else rollfit_tile<DIFFDRIVE, MODE_FUSED>(a, tl.m0, lds);
+            if (al) rollfit_tile<DIFFDRIVE, MODE_FUSED_ALIGNED, 1>(a, tl.m0, lds);
+            else rollfit_tile<DIFFDRIVE, MODE_FUSED, 1>(a, tl.m0, lds);
             break;
     }
 }
