@@ -156,8 +156,9 @@ def cpu_baseline(name, target_s=10.0):
                       f"(sampling, FP64 rollout, reward, weighted update), {dt:.1f} s, single-threaded NumPy"}
 
 
+# the kernels and the host rule that picks their launch shape
 KERNEL_SOURCES = ["paper_2503_12204_amd/csrc/d4_device.hpp", "paper_2503_12204_amd/csrc/d4_kernels.hpp",
-                  "paper_2503_12204_amd/csrc/d4_api.hip"]
+                  "paper_2503_12204_amd/csrc/d4_api.hip", "paper_2503_12204_amd/csrc/d4_host.hpp"]
 
 
 def kernel_source_hash():
