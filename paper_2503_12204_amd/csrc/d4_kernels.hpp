@@ -520,13 +520,16 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
     const uint32_t c2 = (iter << 16) | a.step;
     const uint32_t ebase = (uint32_t)(k * T * DU);
+    // the draw phase, on every replica, reads its uniform operands from VGPR
+    // copies (an SGPR operand halves a VALU instruction's issue rate)
     float ulo[DU], uhi[DU];
 #pragma unroll
     for (int d = 0; d < DU; ++d) {
-        ulo[d] = a.ulo[d];
-        uhi[d] = a.uhi[d];
+        ulo[d] = vgpr_copy(a.ulo[d]);
+        uhi[d] = vgpr_copy(a.uhi[d]);
     }
-    const float sigma = a.sigma, mscale = a.mean_scale;
+    const float sigma = vgpr_copy(a.sigma), mscale = vgpr_copy(a.mean_scale);
+    const PhiloxKey pk = PhiloxKey::make<true>(a.key0, a.key1);
     const int jmax = active ? ((n - 1) >> 1) + ((((n & 1) == 0) && (k < (n >> 1))) ? 1 : 0) : 0;
     const bool pairs_mode = (a.flags & FLAG_SAFE_PAIRS) != 0;
     const size_t Ms = (size_t)M;
@@ -547,7 +550,7 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
         if (active) {
             for (int gi = rep; gi < G_b; gi += R) {
                 float z[4];
-                normal_block(g_a + (uint32_t)gi, (uint32_t)mc, c2, a.inst, a.key0, a.key1, z[0], z[1], z[2], z[3]);
+                normal_blocks<1, true>(g_a + (uint32_t)gi, (uint32_t)mc, c2, a.inst, pk, z);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const uint32_t e = 4 * (g_a + (uint32_t)gi) + (uint32_t)j;
