@@ -14,14 +14,15 @@
 // index fastest, S samples per workgroup (blockDim = n*S).  A lane keeps its
 // robot's state in registers and walks t = 0..T-1; positions of a block of Tb
 // steps go to LDS as [Tb][n][S] float2/float4 slots, one per robot and step
-// (the small footprint keeps three 256-lane workgroups on a CU at Tb = 8 for
-// 16 robots in space), and the pair checks of one step read consecutive slots
+// (a small footprint: two or three 256-lane workgroups share a CU at 16
+// robots in space), and the pair checks of one step read consecutive slots
 // across a wave.  Lane k checks partners (k + j) mod n
 // for j = 1..floor((n-1)/2), plus j = n/2 for k < n/2 when n is even: every
 // unordered pair exactly once, spread evenly.  Each lane also keeps the
 // bounding box of its positions over the block; a partner is checked step by
 // step only when the two boxes come within the threshold (exact in FP32, see
-// box_gap2), which skips nearly all pairs of robots that stay apart.  The
+// box_gap2), which skips nearly all pairs of robots that stay apart, and the
+// kept partners' steps are read from LDS NARROW_STEPS at a time.  The
 // per-(m, t) "robot k hit anything" bits are OR-ed into an LDS word; masks are
 // double buffered, so each time block costs two barriers.
 #pragma once
