@@ -51,6 +51,33 @@ def test_linear_fitness_exponential_tilt():
     assert np.all(np.abs(du_next - expect) <= 4 * se + 1e-12)
 
 
+def test_linear_fitness_through_all_denoising_steps():
+    """Algorithm 1 over all N steps with r = c.u: each step's weighted mean is the
+    exponential tilt (Eq. mc with Gaussian draws), so V_i = Delta U_i / sqrt(abar_i)
+    gains sigma_i^2 c / lambda per step and Delta U_0 = sum_i sigma_i^2 c / lambda
+    (abar_0 = 1).  This pins the chained update and the schedule's scales
+    against each other: an out scale sqrt(abar_i) in place of sqrt(abar_{i-1}),
+    or a mean scale of the wrong step, misses it by about three times the
+    Monte Carlo tolerance."""
+    rng = np.random.default_rng(6)
+    N, D, M, lam = 100, 4, 20_000, 0.1
+    ms, sg, os_ = schedule.step_scalars(N, 1e-4, 1e-2)
+    ab = schedule.alpha_bar(N, 1e-4, 1e-2)
+    c = np.array([0.02, -0.01, 0.0, 0.005])
+    du = np.zeros(D)
+    for i in range(N, 0, -1):
+        eps = rng.normal(size=(D, M))
+        samples = mbd.sample_deformations(du, eps, ms[i], sg[i])
+        du, _ = mbd.mc_update(du, eps, samples @ c, ms[i], sg[i], os_[i], lam, normalize=False)
+    s2 = sum(1.0 / ab[i] - 1.0 for i in range(1, N + 1))
+    expect = s2 * c / lam
+    # each step adds sigma_i times a weighted mean of M standard normals
+    # (near-uniform weights: the tilt |sigma_i c / lambda| stays below 0.2)
+    tol = 6.0 * np.sqrt(s2 / M)
+    assert np.all(np.abs(du - expect) <= tol), (du, expect, tol)
+    assert abs(expect[0]) > 20 * tol
+
+
 def test_quadratic_fitness_posterior_and_smoothed_score():
     """r = -|u - u*|^2 / (2 s): the MC mean tends to the Gaussian posterior mean,
     and Eq. guidance with that mean is the exact score of the noised density."""
