@@ -57,13 +57,13 @@ def test_linear_fitness_through_all_denoising_steps():
     gains sigma_i^2 c / lambda per step and Delta U_0 = sum_i sigma_i^2 c / lambda
     (abar_0 = 1).  This pins the chained update and the schedule's scales
     against each other: an out scale sqrt(abar_i) in place of sqrt(abar_{i-1}),
-    or a mean scale of the wrong step, misses it by about three times the
-    Monte Carlo tolerance."""
+    or a mean scale of the wrong step, misses it by about nine times the
+    Monte Carlo tolerance, a sigma of the wrong step by about twice."""
     rng = np.random.default_rng(6)
     N, D, M, lam = 100, 4, 20_000, 0.1
     ms, sg, os_ = schedule.step_scalars(N, 1e-4, 1e-2)
     ab = schedule.alpha_bar(N, 1e-4, 1e-2)
-    c = np.array([0.02, -0.01, 0.0, 0.005])
+    c = np.array([0.08, -0.04, 0.0, 0.02])
     du = np.zeros(D)
     for i in range(N, 0, -1):
         eps = rng.normal(size=(D, M))
@@ -71,11 +71,40 @@ def test_linear_fitness_through_all_denoising_steps():
         du, _ = mbd.mc_update(du, eps, samples @ c, ms[i], sg[i], os_[i], lam, normalize=False)
     s2 = sum(1.0 / ab[i] - 1.0 for i in range(1, N + 1))
     expect = s2 * c / lam
-    # each step adds sigma_i times a weighted mean of M standard normals
-    # (near-uniform weights: the tilt |sigma_i c / lambda| stays below 0.2)
-    tol = 6.0 * np.sqrt(s2 / M)
+    # each step adds sigma_i times a self-normalised weighted mean of M standard
+    # normals; exponential weights of tilt a inflate its variance by exp(|a|^2)
+    a_max = np.sqrt(1.0 / ab[N] - 1.0) * np.linalg.norm(c) / lam
+    tol = 6.0 * np.sqrt(s2 * np.exp(a_max ** 2) / M)
     assert np.all(np.abs(du - expect) <= tol), (du, expect, tol)
-    assert abs(expect[0]) > 20 * tol
+    assert abs(expect[0]) > 50 * tol
+
+
+def test_planner_loop_with_a_linear_fitness(monkeypatch):
+    """The oracle's own Algorithm 2 loop body (denoise_iteration: Delta U_N = 0,
+    steps N..1 with its Philox draws, then the apply step) with the robot
+    fitness swapped for r = c.u on unclipped controls: Delta U_0 must be the
+    closed form sum_i sigma_i^2 c / lambda of the linear-fitness pin above.
+    Steps taken in increasing order miss it by about three times the
+    tolerance, an index off by one by far more."""
+    from oracle import fitness
+    p, x0, g = W.holo2d_circle(n=1, horizon=2, n_samples=20_000)
+    p = p.replace(flags=0, temperature=0.1)
+    M, D = p.n_samples, p.D
+    c = np.array([0.08, -0.04, 0.0, 0.02])
+    monkeypatch.setattr(dynamics, "clip_controls", lambda prob, u: u)
+    monkeypatch.setattr(dynamics, "rollout", lambda prob, x0_, u: np.asarray(u, dtype=np.float64))
+    monkeypatch.setattr(fitness, "reward", lambda prob, x, goal, pred_dtype=np.float64: (
+        x.reshape(x.shape[0], -1) @ c, np.zeros(x.shape[0], int), np.zeros(x.shape[0], int)))
+    for name in ("success", "at_goal", "objective"):
+        monkeypatch.setattr(fitness, name, lambda prob, x, goal: np.zeros(x.shape[0]))
+    res = mbd.denoise_iteration(p, x0, g, np.zeros(D), 0)
+    ab = schedule.alpha_bar(p.n_steps, p.beta_min, p.beta_max)
+    s2 = sum(1.0 / ab[i] - 1.0 for i in range(1, p.n_steps + 1))
+    expect = s2 * c / p.temperature
+    a_max = np.sqrt(1.0 / ab[p.n_steps] - 1.0) * np.linalg.norm(c) / p.temperature
+    tol = 6.0 * np.sqrt(s2 * np.exp(a_max ** 2) / M)
+    assert np.all(np.abs(res["du0"] - expect) <= tol), (res["du0"], expect, tol)
+    assert np.allclose(res["u"].reshape(-1), res["du0"])
 
 
 def test_quadratic_fitness_posterior_and_smoothed_score():
