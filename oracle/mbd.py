@@ -20,10 +20,12 @@ Pinned by: the closed-form Gaussian tilt of a linear fitness and the
 Gaussian posterior of a quadratic fitness (both reduce the MC estimate to the
 smoothed score of Eq. guidance), the algebraic identity that Eqs. denoising and
 guidance give Eq. mbd-denoising, weights summing to one, uniform weights for
-equal rewards, and the temperature identity of the normalisation
-(tests/test_oracle_mbd.py).  The whole planner beyond one step is "parity
-unpinned": only the chain of pinned steps and the paper's distribution-level
-outcomes speak for it.
+equal rewards, the temperature identity of the normalisation, and, over all
+N steps, the closed form of a linear fitness (the tilt accumulated through the
+schedule) for the chained update and for the loop of denoise_iteration
+(tests/test_oracle_mbd.py).  The planner with the robot fitness beyond one
+step is "parity unpinned": only the chain of pinned steps and the paper's
+distribution-level outcomes speak for it.
 """
 import numpy as np
 
