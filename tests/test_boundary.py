@@ -101,3 +101,25 @@ def test_invalid_obstacles_rejected_without_launch(L):
         mutate(c)
         assert L.lib().d4_noise(ctypes.byref(c), 0, 1, out, None) == L.D4_EINVAL
         assert L.lib().d4_last_error().decode()
+
+
+def test_tile_rule_without_a_gpu():
+    """The launch-shape rule is host code (d4_tile_get makes no GPU call).
+    S = min(64, 256 / n), halved until M / S >= 256; with the full S the time
+    block keeps the positions near 32 KiB (2D, 8-byte slots), or near 48 KiB
+    for a single 3D problem (16-byte slots); with a halved S, R = min(16,
+    1024 / (S n)) replica lanes and the longest block that fits (up to 64)."""
+    import bench
+    from paper_2503_12204_amd import autotune as AT
+    expect = {
+        # name: (single problem, batched rule)
+        "holo3d_sphere_swap": ((16, 12, 1), (16, 8, 1)),     # 48 KiB / (16 * 16 * 16 B) = 12
+        "unicycle_random": ((8, 64, 16), (32, 16, 1)),       # M = 2048: S 32 -> 8, R = 1024 / 64
+        "holo2d_circle_swap": ((1, 64, 16), (64, 16, 1)),    # M = 256: S 64 -> 1, R = 16
+        "diffdrive_circle_swap": ((16, 16, 1), (16, 16, 1)),  # 32 KiB / (16 * 16 * 8 B) = 16
+        "holo2d_circle_obstacles": ((16, 16, 1), (16, 16, 1)),
+    }
+    for name, (single, batched) in expect.items():
+        p, _, _ = bench.make_workload(name)
+        assert AT.get_tile(p) == single, name
+        assert AT.get_tile(p, batched=True) == batched, name
