@@ -178,3 +178,70 @@ def test_planner_improves_circle_swap():
     base = mbd.apply_deformation(p, x0, g, u0, np.zeros(p.D))
     u, hist = mbd.plan(p, x0, g, iterations=1)
     assert hist[0]["r"] > base["r"] + 0.2
+
+
+def _deformation_case():
+    """One 2D double integrator, two steps, a non-zero plan tau.u and a
+    deformation whose sum with it leaves the control box |a| <= 1 on three of
+    four components.  Expected controls and states are worked out by hand:
+    clip(tau.u + Delta U) = [[1.0, -0.6], [-0.3, -1.0]], and the double
+    integrator from rest gives p1 = a0 dt^2 / 2, v1 = a0 dt,
+    p2 = p1 + v1 dt + a1 dt^2 / 2, v2 = v1 + a1 dt (RK4 is exact for it)."""
+    p = W.Problem(dyn=W.HOLO2D, n_robots=1, horizon=2, n_samples=1, dt=0.1, v_max=2.0,
+                  u_lo=(-1.0, -1.0, -1.0), u_hi=(1.0, 1.0, 1.0), flags=0)
+    x0 = np.zeros((1, 4))
+    goal = np.array([[1.0, 0.0]])
+    tau_u = np.array([[0.7, -0.5], [0.2, -0.9]])
+    du = np.array([[0.6, -0.1], [-0.5, -0.4]])
+    u_expect = np.array([[1.0, -0.6], [-0.3, -1.0]])
+    x_expect = np.array([[0.0, 0.0, 0.0, 0.0],
+                         [0.005, -0.003, 0.1, -0.06],
+                         [0.0135, -0.014, 0.07, -0.16]])
+    return p, x0, goal, tau_u, du, u_expect, x_expect
+
+
+def test_effective_controls_clip_the_sum_with_the_plan():
+    """Algorithm 2 rolls out tau.u + Delta U^(m), clipped per component
+    (reading R8): the clip applies to the sum, not to the deformation alone,
+    and the plan is not dropped.  Clipping Delta U before adding tau.u gives
+    [[1.3, -0.6], [-0.3, -1.3]]; dropping tau.u gives Delta U itself."""
+    p, x0, goal, tau_u, du, u_expect, x_expect = _deformation_case()
+    u = mbd.effective_controls(p, tau_u.reshape(-1), du.reshape(1, -1))
+    assert u.shape == (1, 1, 2, 2)
+    assert np.allclose(u[0, 0], u_expect, rtol=0, atol=1e-15)
+    x = dynamics.rollout(p, x0, u)
+    assert np.allclose(x[0, 0], x_expect, rtol=0, atol=1e-15)
+
+
+def test_apply_deformation_closed_form_with_a_binding_box():
+    """The iteration's update tau.u <- clip(tau.u + Delta U_0) and the rollout
+    of the new plan (Algorithm 2), against the hand-worked controls and the
+    double integrator's closed-form states; the reward follows Eq.
+    generic-reward with d0 = |p_0 - g| = 1 and no partners."""
+    p, x0, goal, tau_u, du, u_expect, x_expect = _deformation_case()
+    res = mbd.apply_deformation(p, x0, goal, tau_u.reshape(-1), du.reshape(-1))
+    assert np.allclose(res["u"][0], u_expect, rtol=0, atol=1e-15)
+    assert np.allclose(res["x"][0], x_expect, rtol=0, atol=1e-15)
+    d1 = np.hypot(1.0 - 0.005, 0.003)
+    d2 = np.hypot(1.0 - 0.0135, 0.014)
+    assert abs(res["r"] - ((1.0 - d1) + (1.0 - d2)) / 2.0) < 1e-15
+    assert res["hits"] == 0 and res["success"] and not res["at_goal"]
+
+
+def test_one_sample_step_moves_the_plan_by_its_own_deformation():
+    """With M = 1 the softmax weight is 1 whatever the reward, so one
+    denoising step returns sqrt(abar_{i-1}) (Delta U_i / sqrt(abar_i)
+    + sigma_i eps) (Eq. mbd-denoising) and rolls out clip(tau.u + that sample)
+    (Algorithm 1 sampling and rollout steps): the rollout of the step is the
+    closed-form trajectory of the clipped sum."""
+    p, x0, goal, tau_u, du, u_expect, x_expect = _deformation_case()
+    p = p.replace(n_steps=4)
+    ms, sg, os_ = schedule.step_scalars(p.n_steps, p.beta_min, p.beta_max)
+    i = 3
+    eps = np.array([[0.5], [-1.0], [2.0], [0.25]])
+    # choose Delta U_i so that the sample equals du exactly
+    du_i = (du.reshape(-1) - sg[i] * eps[:, 0]) / ms[i]
+    out = mbd.denoise_step(p, x0, goal, tau_u.reshape(-1), du_i, 0, i, eps=eps)
+    assert np.allclose(out["w"], [1.0])
+    assert np.allclose(out["du_next"], os_[i] * du.reshape(-1), rtol=1e-14, atol=1e-15)
+    assert np.allclose(out["x"][0, 0], x_expect, rtol=0, atol=1e-14)

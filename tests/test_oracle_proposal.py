@@ -102,3 +102,31 @@ def test_quantised_path_is_close_and_exact_on_representable_inputs():
     # with identity quantisation the two paths coincide
     yi, _ = P.forward(params, x, seg, 2, quant=lambda a: a)
     assert np.array_equal(yi, y)
+
+
+def test_forward_hand_computed_value():
+    """One layer of width 2 (hidden 2) on two instances, worked out by hand:
+    instance 0 holds robots x = (1, 0) and (0, 2), instance 1 the robot (1, 1).
+    The pool averages the layer's input h_0 over the robot's own instance
+    (mean over instance 0: (1.0, 0.5)); pooling the layer's output instead, or
+    over all robots, changes every value below.
+
+    h_0 = x We + be: (1.5, -0.5), (0.5, 1.5), (1.5, 0.5)
+    relu(h_0 W1 + b1): (0.5, 0), (3.5, 0), (2.5, 0)
+    relu(.) W2 + b2: (0.75, 1.0), (3.75, 7.0), (2.75, 5.0)
+    mean(h_0) Wp: (0.5, 1.0), (0.5, 1.0), (0.5, 1.5)
+    h_1: (2.75, 1.5), (4.75, 9.5), (4.75, 7.0)
+    y = h_1 Wh + bh: 1.75, -4.25, -1.75
+    """
+    params = {
+        "We": np.eye(2), "be": np.array([0.5, -0.5]),
+        "W1_0": np.array([[1.0, -1.0], [2.0, 0.0]]), "b1_0": np.array([0.0, -1.0]),
+        "W2_0": np.array([[1.0, 2.0], [3.0, 4.0]]), "b2_0": np.array([0.25, 0.0]),
+        "Wp_0": np.array([[0.0, 1.0], [1.0, 0.0]]),
+        "Wh": np.array([[1.0], [-1.0]]), "bh": np.array([0.5]),
+    }
+    x = np.array([[1.0, 0.0], [0.0, 2.0], [1.0, 1.0]])
+    seg = np.array([0, 2, 3])
+    y, cache = P.forward(params, x, seg, layers=1)
+    assert np.array_equal(y[:, 0], [1.75, -4.25, -1.75])
+    assert np.array_equal(cache["h"][1], [[2.75, 1.5], [4.75, 9.5], [4.75, 7.0]])
