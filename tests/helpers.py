@@ -86,4 +86,11 @@ def problems_small():
     p, x0, g = W.random_instance(rng, W.HOLO3D, 6, 30, 90, box=3.0, min_sep=0.7,
                                  obstacles=((1.5, 1.5, 1.5, 0.5), (0.5, 2.5, 1.0, 0.3)))
     out.append(("holo3d_obs2_n6_T30_M90", p, x0, g))
+    # the longest horizon of the batched workloads (160 steps): the heading of
+    # the unicycle and of the differential drive is not wrapped, so late steps
+    # take sines and cosines of angles up to |omega| T dt = 16 pi
+    p, x0, g = W.random_instance(rng, W.UNICYCLE, 8, 160, 128, box=6.0, min_sep=0.8)
+    out.append(("unicycle_n8_T160_M128", p, x0, g))
+    p, x0, g = W.random_instance(rng, W.DIFFDRIVE, 12, 160, 96, box=6.0, min_sep=0.8)
+    out.append(("diffdrive_n12_T160_M96", p, x0, g))
     return out

@@ -106,3 +106,78 @@ def test_first_success_experiment_runs(L):
         assert r["runs"] == 2 and 0.0 <= r["solved_fraction"] <= 1.0
         assert len(r["iterations_of_solved_runs"]) == round(2 * r["solved_fraction"])
         assert all(1 <= k <= 20 for k in r["iterations_of_solved_runs"])
+
+
+def test_batch_nonfinite_instance_is_flagged_alone(L):
+    """An instance with a NaN goal gets status D4_ENONFINITE; its neighbours in
+    the same launches keep status 0 and their single-problem results."""
+    inst = _mix(3, 128, 6, seed=5, t_range=(10, 30))
+    p, x0, g = inst[1]
+    g = g.copy()
+    g[0, 0] = np.nan
+    inst[1] = (p, x0, g)
+    probs = [q for q, _, _ in inst]
+    print("case batch with one NaN goal", [(q.dyn, q.n_robots, q.horizon) for q in probs], flush=True)
+    bc = L.BatchContext(probs, [x for _, x, _ in inst], [gg for _, _, gg in inst])
+    stats = bc.iterate(0)
+    got = [bc.plan_of(j).cpu().numpy() for j in range(len(probs))]
+    bc.close()
+    assert stats[1]["status"] == L.D4_ENONFINITE
+    from paper_2503_12204_amd import autotune as AT
+    for j in (0, 2):
+        q, x0, g = inst[j]
+        assert stats[j]["status"] == 0
+        S, Tb, R = AT.get_tile(q, batched=True)
+        AT.set_tile(q.dyn, q.n_robots, q.horizon, S, Tb, R)
+        try:
+            u, hist = L.plan(q, x0, g, iterations=1)
+        finally:
+            AT.clear_tile(q.dyn, q.n_robots, q.horizon)
+        assert np.array_equal(u.cpu().numpy(), got[j]) and hist[0] == stats[j]
+
+
+@pytest.mark.parametrize("dyn", [W.HOLO2D, W.HOLO3D, W.UNICYCLE])
+def test_batch_largest_instance_against_oracle(L, dyn):
+    """The largest instance shape of the 512-instance workload (32 robots, 160
+    steps, 1024 samples): the fused step of the single-problem path matches
+    the oracle on sampled samples (draws bit-exact, rewards and counts within
+    their bars), and the same instance inside a batch reproduces that path's
+    iteration bit for bit."""
+    from paper_2503_12204_amd import autotune as AT
+    rng = np.random.default_rng(32 + dyn)
+    p, x0, g = W.random_instance(rng, dyn, 32, 160, 1024, box=10.0, min_sep=1.0)
+    p = p.replace(n_steps=3, instance_id=11)
+    print(f"case largest batch instance dyn={dyn} n=32 T=160 M=1024", flush=True)
+    u_base = rng.uniform(-0.3, 0.3, size=p.D).astype(np.float32)
+    du = (rng.normal(size=p.D) * 0.2).astype(np.float32)
+    cu = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    eps, r, hits = L.sample_rollout_fitness(p, cu(x0), cu(g), cu(u_base), cu(du), 2, 3)
+    torch.cuda.synchronize()
+    idx = np.sort(rng.choice(p.n_samples, size=24, replace=False))
+    idx[0], idx[-1] = 0, p.n_samples - 1
+    ora = ombd.sample_rewards(p, x0, g, u_base, du, 2, 3, samples=idx)
+    assert np.array_equal(eps.cpu().numpy()[:, idx], ora["eps"])
+    from helpers import REWARD_ATOL, ambiguous_band_pairs, ambiguous_samples
+    amb = ambiguous_samples(p, ora["x"])
+    rg, hg = r.cpu().numpy()[idx], hits.cpu().numpy()[idx]
+    ok = ~amb
+    assert ok.sum() >= 6
+    assert np.all(np.abs(rg[ok] - ora["r"][ok]) <= REWARD_ATOL)
+    assert np.array_equal(hg[ok], ora["hits"][ok])
+    assert np.all(np.abs(hg[amb] - ora["hits"][amb]) <= ambiguous_band_pairs(p, ora["x"])[amb])
+    # inside a batch with a small neighbour
+    q, xq, gq = _mix(1, 1024, 3, seed=9)[0]
+    probs = [p, q.replace(instance_id=12)]
+    bc = L.BatchContext(probs, [x0, xq], [g, gq])
+    plans = [u_base.reshape(p.n_robots, p.horizon, p.du), np.zeros((q.n_robots, q.horizon, q.du), np.float32)]
+    bc.set_plans(plans)
+    stats = bc.iterate(0)
+    got = bc.plan_of(0).cpu().numpy()
+    bc.close()
+    S, Tb, R = AT.get_tile(p, batched=True)
+    AT.set_tile(p.dyn, p.n_robots, p.horizon, S, Tb, R)
+    try:
+        u, hist = L.plan(p, x0, g, iterations=1, u_init=plans[0])
+    finally:
+        AT.clear_tile(p.dyn, p.n_robots, p.horizon)
+    assert np.array_equal(u.cpu().numpy(), got) and hist[0] == stats[0]

@@ -515,3 +515,69 @@ def test_sixteen_obstacles_with_tiny_workgroups(L):
     for S, Tb, R, u, rew, oh in plans[1:]:
         assert np.array_equal(u, plans[0][3]), f"tile {(S, Tb, R)}"
         assert rew == plans[0][4] and oh == plans[0][5]
+
+
+@pytest.mark.parametrize("dyn", [W.UNICYCLE, W.DIFFDRIVE])
+def test_late_horizon_heading(L, dyn):
+    """160 steps turning at the control bound: the unwrapped heading reaches
+    about 16 pi.  Every single step, from the GPU's own state, stays within
+    the step bar (Sec. V models), and the fused step's draws and rewards meet
+    their bars at that horizon."""
+    rng = np.random.default_rng(160 + dyn)
+    p, x0, g = W.random_instance(rng, dyn, 6, 160, 64, box=5.0, min_sep=0.8)
+    print(f"case late heading dyn={dyn} n=6 T=160 M=64", flush=True)
+    om = 1 if dyn == W.UNICYCLE else 0   # index of omega in u
+    u = _rand_controls(rng, p, p.n_samples, spread=0.9)
+    u[..., om] = np.float32(p.u_hi[om]) * rng.uniform(0.9, 1.2, size=u.shape[:-1]).astype(np.float32)
+    x = _np(L.rollout(p, _cu(x0), _cu(u))).astype(np.float64)
+    assert np.abs(x[:, :, -1, 2]).max() > 14 * np.pi
+    uc = odyn.clip_controls(p, u.astype(np.float64))
+    for t in range(p.horizon):
+        ref = odyn.step(p, x[:, :, t], uc[:, :, t])
+        err = np.abs(x[:, :, t + 1] - ref)
+        assert np.all(err <= STEP_RTOL * np.abs(ref) + STEP_ATOL), f"t={t} max err {err.max()}"
+    ref = odyn.rollout(p, x0, u)
+    assert np.abs(x - ref).max() <= 2e-6 * p.horizon * (1.0 + np.abs(ref).max())
+    # fused step: the plan turns at the bound, the draws add sigma_i eps
+    ub = np.zeros((p.n_robots, p.horizon, p.du), np.float32)
+    ub[..., om] = np.float32(p.u_hi[om])
+    ub = ub.reshape(-1)
+    du = (rng.normal(size=p.D) * 0.1).astype(np.float32)
+    eps, r, hits = L.sample_rollout_fitness(p, _cu(x0), _cu(g), _cu(ub), _cu(du), 1, 30)
+    ora = ombd.sample_rewards(p, x0, g, ub, du, 1, 30)
+    assert np.abs(ora["x"][:, :, -1, 2]).max() > 14 * np.pi
+    assert np.array_equal(_np(eps), ora["eps"])
+    _check_rewards(p, ora, _np(r), _np(hits))
+
+
+def test_nonfinite_reward_sets_status(L):
+    """A NaN goal makes every reward non-finite: the update kernels set the
+    iteration's status to D4_ENONFINITE (the non-finite check of the batch
+    statistics) and every kernel still runs to completion, so the same
+    context then runs the finite problem with status 0 and the plan of a
+    fresh context."""
+    p, x0, g = W.holo2d_circle(n=4, horizon=20, n_samples=128)
+    p = p.replace(n_steps=8)
+    bad = g.copy()
+    bad[1, 0] = np.nan
+    print("case non-finite goal n=4 T=20 M=128 N=8", flush=True)
+    ctx = L.Context(p)
+    u = torch.zeros((p.n_robots, p.horizon, p.du), dtype=torch.float32, device="cuda")
+    st = ctx.denoise_iter(_cu(x0), _cu(bad), u, 0)
+    assert st["status"] == L.D4_ENONFINITE
+    assert not np.isfinite(st["reward"])
+    u = torch.zeros_like(u)
+    st = ctx.denoise_iter(_cu(x0), _cu(g), u, 0)
+    ctx.close()
+    assert st["status"] == 0 and np.isfinite(st["reward"])
+    ctx = L.Context(p)
+    u2 = torch.zeros_like(u)
+    st2 = ctx.denoise_iter(_cu(x0), _cu(g), u2, 0)
+    ctx.close()
+    assert np.array_equal(_np(u), _np(u2)) and st == st2
+    # the split update call flags nothing but still yields finite uniform weights
+    eps = L.noise(p, 0, 3)
+    r = torch.full((p.n_samples,), float("nan"), device="cuda")
+    du_out, w = L.score_update(p, r, eps, torch.zeros(p.D, device="cuda"), 3)
+    assert np.allclose(_np(w), 1.0 / p.n_samples, rtol=1e-6)
+    assert np.isfinite(_np(du_out)).all()
