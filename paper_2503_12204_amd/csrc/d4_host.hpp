@@ -274,10 +274,13 @@ inline size_t rollfit_lds(const d4_problem* p, Tile t) {
     const size_t n = p->n_robots;
     const size_t slot = s.dp == 3 ? 16 : 8;
     if (t.R > 1) return coop_lds(p->dyn, n, t.S, t.Tb, t.R);
-    // one-lane kernel: positions [Tb][n][S], boxes [n][S][2], masks [2][Tb][S], flags [2][S]
+    // one-lane kernel: positions [Tb][n][S], boxes [n][S][2], masks [2][Tb][S], flags [2][S],
+    // hit counters [S], then per wave a list of 64 floor(n/2) 16-bit narrow-phase triples
+    const size_t waves = (n * t.S + 63) / 64;
     const size_t a = (size_t)t.Tb * n * t.S * slot + (size_t)2 * n * t.S * slot +
-                     (size_t)2 * t.Tb * t.S * 4 + (size_t)2 * t.S * 4;
-    const size_t b = (size_t)4 * n * t.S * 4;
+                     (size_t)2 * t.Tb * t.S * 4 + (size_t)2 * t.S * 4 + (size_t)t.S * 4 +
+                     waves * 64 * (n / 2) * 2;
+    const size_t b = (size_t)3 * n * t.S * 4;
     return a > b ? a : b;
 }
 

@@ -191,6 +191,9 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     PT* box = pos + Tb * n * S;                                                  // [n][S][lo, hi]
     uint32_t* mask = reinterpret_cast<uint32_t*>(box + 2 * n * S);              // [2][Tb][S]
     uint32_t* anyhit = mask + 2 * Tb * S;                                        // [2][S]
+    int* hitc = reinterpret_cast<int*>(anyhit + 2 * S);                          // [S] pair hits per sample
+    const int wave = tid >> 6, lane = tid & 63;
+    uint16_t* items = reinterpret_cast<uint16_t*>(hitc + S) + wave * (64 * (n >> 1));  // [waves][64 (n/2)]
 
     float x[DX], aux[DY::AUX], g[DP];
     if (FROM_X) {
@@ -207,7 +210,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     const float inv_d0 = inv_start_dist(goal_d2<DP>(x, g), a.d0_floor);
 
     float goal_acc = 0.0f;
-    int safe_cnt = 0, hit_cnt = 0, obs_cnt = 0;
+    int safe_cnt = 0, obs_cnt = 0;
     __shared__ float4 obs_l[MAX_OBS];
     // the obstacle count is uniform over the grid, so the barrier is too
     if (a.n_obs > 0) {
@@ -215,6 +218,8 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
         __syncthreads();
     }
     const int n_obs = a.n_obs;
+    // pair-hit counters; the first block's barrier orders this before any update
+    if (k_raw == 0) hitc[ms] = 0;
 
     const uint32_t iter = a.iter_dev ? *a.iter_dev : a.iter;
     const uint32_t c2 = (iter << 16) | a.step;
@@ -388,45 +393,63 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
                 l = l + 1 < n ? l + 1 : 0;
             }
         }
-        // narrow phase: exact checks of those partners at every step of the
-        // block, four steps at a time, so that the LDS reads of the four steps
-        // are in flight together (the mask updates come after the reads)
-        if (near) {
-            bool any = false;
-            for (int tt0 = 0; tt0 < tcount; tt0 += NS) {
-                float pk[NS][DP];
-#pragma unroll
-                for (int q = 0; q < NS; ++q) {
-                    const int tt = tt0 + q < tcount ? tt0 + q : tcount - 1;
-                    PS::unpack(pos[(tt * n + k) * S + ms], pk[q]);
+        // narrow phase: exact checks of the kept partners at every step of the
+        // block.  The wave lists its kept (robot, sample, partner) triples in
+        // LDS, ordered by partner and lane (ballot and lane count per partner
+        // index), and its lanes then take them in turn, so that the checks
+        // are spread over the wave instead of waiting on the lane with the
+        // most kept partners.  Each triple reads NS steps' positions from
+        // LDS together before its compares.  Hits are OR-ed into the step's
+        // collision mask for both robots and counted per sample; the order of
+        // these integer updates does not change their result.
+        if (__ballot(near != 0u)) {
+            const int jw = n >> 1;
+            int total = 0;
+            for (int j = 0; j < jw; ++j) {
+                const bool has = (near >> j) & 1u;
+                const uint64_t bal = __ballot(has);
+                if (bal) {
+                    if (has) {
+                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        items[total + (int)below] = (uint16_t)((k << 10) | (ms << 4) | j);
+                    }
+                    total += __popcll(bal);
                 }
-                uint32_t bits[NS];
-#pragma unroll
-                for (int q = 0; q < NS; ++q) bits[q] = 0u;
-                uint32_t nb = near;
-                while (nb) {
-                    const int j = __builtin_ctz(nb);
-                    nb &= nb - 1u;
-                    int l = k + 1 + j;
-                    l = l >= n ? l - n : l;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // the last wave of a workgroup can hold fewer than 64 lanes
+            const int wlanes = min(64, (int)blockDim.x - wave * 64);
+            for (int i = lane; i < total; i += wlanes) {
+                const uint32_t code = items[i];
+                const int ki = (int)(code >> 10), mi = (int)((code >> 4) & 63u);
+                int l = ki + 1 + (int)(code & 15u);
+                l = l >= n ? l - n : l;
+                const uint32_t pair = (1u << ki) | (1u << l);
+                int cnt = 0;
+                for (int tt0 = 0; tt0 < tcount; tt0 += NS) {
+                    float pa[NS][DP], pb[NS][DP];
 #pragma unroll
                     for (int q = 0; q < NS; ++q) {
                         const int tt = tt0 + q < tcount ? tt0 + q : tcount - 1;
-                        float pl[DP];
-                        PS::unpack(pos[(tt * n + l) * S + ms], pl);
-                        bits[q] |= (pair_d2<DP>(pk[q], pl) <= a.thr2) ? (1u << l) : 0u;
+                        PS::unpack(pos[(tt * n + ki) * S + mi], pa[q]);
+                        PS::unpack(pos[(tt * n + l) * S + mi], pb[q]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        if (tt0 + q < tcount && pair_d2<DP>(pa[q], pb[q]) <= a.thr2) {
+                            atomicOr(&mask[(buf * Tb + tt0 + q) * S + mi], pair);
+                            ++cnt;
+                        }
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < NS; ++q) {
-                    if (tt0 + q < tcount && bits[q]) {
-                        hit_cnt += __popc(bits[q]);
-                        atomicOr(&mask[(buf * Tb + tt0 + q) * S + ms], bits[q] | (1u << k));
-                        any = true;
-                    }
+                if (cnt) {
+                    atomicAdd(&hitc[mi], cnt);
+                    atomicOr(&anyhit[buf * S + mi], 1u);
                 }
             }
-            if (any) atomicOr(&anyhit[buf * S + ms], 1u);
         }
         __syncthreads();
         if (active && anyhit[buf * S + ms])
@@ -436,22 +459,20 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
     __syncthreads();
     float* rg = lds;
     int* rs = reinterpret_cast<int*>(lds + n * S);
-    int* rh = rs + n * S;
-    int* ro = rh + n * S;
+    int* ro = rs + n * S;
     if (active) {
         rg[k * S + ms] = goal_acc;
         rs[k * S + ms] = safe_cnt;
-        rh[k * S + ms] = hit_cnt;
         ro[k * S + ms] = obs_cnt;
     }
     __syncthreads();
     if (k_raw == 0 && live) {
         float gs = 0.0f;
-        int ss = 0, hs = 0, os = 0;
+        int ss = 0, os = 0;
+        const int hs = hitc[ms];
         for (int kk = 0; kk < n; ++kk) {
             gs += rg[kk * S + ms];
             ss += rs[kk * S + ms];
-            hs += rh[kk * S + ms];
             os += ro[kk * S + ms];
         }
         const float pen = (float)((pairs_mode ? 2 * hs : ss) + os);
