@@ -108,6 +108,24 @@ typedef struct d4_ctx d4_ctx;
 /* Message of the last failed call on this thread ("" if none). */
 const char* d4_last_error(void);
 
+/* Process-wide launch options.  None changes a result; each exists so that
+ * tests can check that two launch forms agree bit for bit.
+ *  D4_OPT_GRAPHS        1 (default): d4_denoise_iter and d4_batch_iter replay a
+ *                       HIP graph captured on their first call; 0: they enqueue
+ *                       the same launches directly on the caller's stream.
+ *  D4_OPT_ALIGNED_DRAWS 1 (default): problems whose robots' draws start on a
+ *                       Philox block (T d_u a multiple of 4) use the fused
+ *                       kernel's whole-block draw window; 0: every problem uses
+ *                       the general window.
+ *  D4_OPT_UPDATE_GRID   0 (default): the update kernel's grid follows its rule
+ *                       (at most 512 workgroups of two rows each); n > 0: n
+ *                       workgroups (capped at D).
+ * d4_set_option returns D4_EINVAL for an unknown option or a value outside the
+ * ranges above; d4_get_option writes the current value to *value (host). */
+enum { D4_OPT_GRAPHS = 0, D4_OPT_ALIGNED_DRAWS = 1, D4_OPT_UPDATE_GRID = 2 };
+int32_t d4_set_option(int32_t option, int32_t value);
+int32_t d4_get_option(int32_t option, int32_t* value);
+
 /*
  * Standard normal draws of one denoising step (the sampling step of
  * Algorithm 1, Eq. mc).  eps[e][m], e < D, m < M, [D][M] layout.
@@ -219,7 +237,11 @@ int32_t d4_tile_get(const d4_problem* p, int32_t batched, int32_t* samples_per_g
  * arrays; the broad phase of the pair checks makes the cost depend on where
  * the robots are), with zero controls.  Scratch buffers are allocated and
  * freed here; synchronises the null stream.  Installs the fastest tile and
- * reports it (outputs are host pointers, each may be NULL). */
+ * reports it (outputs are host pointers, each may be NULL).  The library
+ * keeps installed tiles in memory only: the persistent cache of tuned tiles
+ * (keyed by architecture, kernel source version and problem shape) is the
+ * Python layer's (paper_2503_12204_amd/autotune.py), which reinstalls them
+ * with d4_tile_set, so this call takes no cache path. */
 int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int32_t reps,
                     int32_t* samples_per_group, int32_t* steps_per_block, int32_t* replicas, float* best_us);
 
@@ -239,7 +261,8 @@ typedef struct d4_batch d4_batch;
 
 /* probs: host array of `count` problems (copied).  Allocates the workspace:
  * sum_j D_j * M floats of draws dominate.  D4_EINVAL if sampler settings
- * differ between instances. */
+ * differ between instances.  There is no options argument: launch shapes come
+ * from the shared tile rule and d4_set_option. */
 int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** batch);
 
 /* Host outputs (each may be NULL): per-instance float offsets of the packed
@@ -288,7 +311,10 @@ typedef struct d4p_net d4p_net;
 int32_t d4p_create(const d4p_config* cfg, d4p_net** net);
 int32_t d4p_destroy(d4p_net* net);
 int32_t d4p_num_params(const d4p_net* net, int64_t* count);       /* count: host */
-/* params: device [count] FP32 in the flat order above; set also resets Adam. */
+/* params: device [count] FP32 in the flat order above; set also resets Adam.
+ * These two calls are the network's save and load: the library writes no
+ * files, so a caller stores the flat vector (with the d4p_config that shapes
+ * it) in its own format and sets it back into a network of the same config. */
 int32_t d4p_set_params(d4p_net* net, const float* params, void* stream);
 int32_t d4p_get_params(const d4p_net* net, float* params, void* stream);
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libd4.so")
 
 D4_OK, D4_EINVAL, D4_ENOMEM, D4_EHIP, D4_ENONFINITE, D4_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MAX_OBSTACLES = 16
+OPTIONS = {"graphs": 0, "aligned_draws": 1, "update_grid": 2}
 
 
 class D4Error(RuntimeError):
@@ -53,6 +54,8 @@ def _load():
     fp = c_void_p
     sig = {
         "d4_last_error": ([], ctypes.c_char_p),
+        "d4_set_option": ([c_int32, c_int32], c_int32),
+        "d4_get_option": ([c_int32, POINTER(c_int32)], c_int32),
         "d4_noise": ([P, c_uint32, c_uint32, fp, c_void_p], c_int32),
         "d4_box_muller": ([fp, ctypes.c_int64, fp, c_void_p], c_int32),
         "d4_rollout": ([P, fp, fp, fp, c_void_p], c_int32),
@@ -84,6 +87,33 @@ def lib():
 def _check(rc):
     if rc != D4_OK:
         raise D4Error(rc, _lib.d4_last_error().decode())
+
+
+def set_option(name: str, value: int):
+    """d4_set_option by name: graphs, aligned_draws, update_grid."""
+    _check(_lib.d4_set_option(OPTIONS[name], int(value)))
+
+
+def get_option(name: str) -> int:
+    v = c_int32()
+    _check(_lib.d4_get_option(OPTIONS[name], ctypes.byref(v)))
+    return v.value
+
+
+class option:
+    """Context manager that sets a launch option and restores it on exit."""
+
+    def __init__(self, name: str, value: int):
+        self.name, self.value = name, value
+
+    def __enter__(self):
+        self.old = get_option(self.name)
+        set_option(self.name, self.value)
+        return self
+
+    def __exit__(self, *exc):
+        set_option(self.name, self.old)
+        return False
 
 
 def to_c(p: Problem) -> D4Problem:

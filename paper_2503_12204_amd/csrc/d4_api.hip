@@ -70,7 +70,7 @@ int launch_rollfit(const d4_problem* p, const RollFitArgs& a, Tile tile, hipStre
         HIP_LAUNCH_CHECK("k_rollfit_coop");
         return D4_OK;
     }
-    const bool al = draws_aligned(p) && !std::getenv("D4_NO_ALIGNED");
+    const bool al = draws_aligned(p) && g_opt_aligned_draws.load() != 0;
     switch (p->dyn) {
         case HOLO2D: launch_rollfit_dyn<HOLO2D>(FROM_X, al, grid, block, lds, st, a); break;
         case HOLO3D: launch_rollfit_dyn<HOLO3D>(FROM_X, al, grid, block, lds, st, a); break;
@@ -106,7 +106,7 @@ int launch_update(const d4_problem* p, const float* eps, const float* r, const f
     const int J = upd_reg_j(M, eps, r);
     if (J > 0) {
         int grid = std::max(1, std::min(512, (D + UPD_ROWS - 1) / UPD_ROWS));
-        if (const char* e = std::getenv("D4_UPD_GRID")) grid = std::max(1, std::min(D, std::atoi(e)));
+        if (const int g = g_opt_update_grid.load()) grid = std::max(1, std::min(D, g));
         switch (J) {
             case 1: hipLaunchKernelGGL(k_softmax_update_reg<1>, dim3(grid), dim3(256), 0, st, a); break;
             case 2: hipLaunchKernelGGL(k_softmax_update_reg<2>, dim3(grid), dim3(256), 0, st, a); break;
@@ -150,8 +150,20 @@ void free_ctx_buffers(d4_ctx* c) {
     if (c->iter) (void)hipFree(c->iter);
 }
 
+// Field by field (a byte compare would also compare padding, which C callers
+// need not initialise).  Floats compare by value; obstacles past n_obstacles
+// are ignored.
 bool same_problem(const d4_problem& a, const d4_problem& b) {
-    return std::memcmp(&a, &b, sizeof(d4_problem)) == 0;
+    bool eq = a.dyn == b.dyn && a.n_robots == b.n_robots && a.horizon == b.horizon && a.n_samples == b.n_samples &&
+              a.n_steps == b.n_steps && a.dt == b.dt && a.robot_radius == b.robot_radius &&
+              a.safety_margin == b.safety_margin && a.w_safe == b.w_safe && a.temperature == b.temperature &&
+              a.beta_min == b.beta_min && a.beta_max == b.beta_max && a.v_max == b.v_max &&
+              a.goal_tol == b.goal_tol && a.d0_floor == b.d0_floor && a.flags == b.flags &&
+              a.instance_id == b.instance_id && a.seed == b.seed && a.n_obstacles == b.n_obstacles;
+    for (int d = 0; d < 3 && eq; ++d) eq = a.u_lo[d] == b.u_lo[d] && a.u_hi[d] == b.u_hi[d];
+    for (int o = 0; o < a.n_obstacles && eq; ++o)
+        for (int c = 0; c < 4; ++c) eq = eq && a.obstacles[o][c] == b.obstacles[o][c];
+    return eq;
 }
 
 bool same_shape(const d4_problem& a, const d4_problem& b) {
@@ -159,9 +171,20 @@ bool same_shape(const d4_problem& a, const d4_problem& b) {
            a.n_samples == b.n_samples && a.n_steps == b.n_steps;
 }
 
-// Enqueue one full iteration on `st` using only ctx-owned buffers.
-int enqueue_iteration(d4_ctx* c, hipStream_t st) {
-    const d4_problem* p = &c->prob;
+// Device buffers of one iteration: problem inputs, the plan (updated in
+// place), the workspace and the outputs.
+struct IterBuffers {
+    const float* x0;
+    const float* goal;
+    float* ubase;
+    float *eps, *r, *du_a, *du_b, *traj, *stats;
+    int *hits, *status;
+    uint32_t* iter;
+};
+
+// Enqueue one full iteration of problem p on `st`.
+int enqueue_iteration(const d4_problem* p, const IterBuffers& c_, hipStream_t st) {
+    const IterBuffers* c = &c_;
     const Shape s = shape_of(p->dyn);
     const int D = p->n_robots * p->horizon * s.du;
     const Schedule sc = make_schedule(p);
@@ -233,10 +256,24 @@ int enqueue_iteration(d4_ctx* c, hipStream_t st) {
     return D4_OK;
 }
 
-bool graphs_disabled() {
-    const char* e = std::getenv("D4_NO_GRAPH");
-    return e && e[0] == '1';
+IterBuffers ctx_buffers(d4_ctx* c) {
+    IterBuffers b;
+    b.x0 = c->x0;
+    b.goal = c->goal;
+    b.ubase = c->ubase;
+    b.eps = c->eps;
+    b.r = c->r;
+    b.du_a = c->du_a;
+    b.du_b = c->du_b;
+    b.traj = c->traj;
+    b.stats = c->stats;
+    b.hits = c->hits;
+    b.status = c->status;
+    b.iter = c->iter;
+    return b;
 }
+
+bool graphs_disabled() { return g_opt_graphs.load() == 0; }
 
 }  // namespace
 
@@ -244,6 +281,34 @@ bool graphs_disabled() {
 extern "C" {
 
 const char* d4_last_error(void) { return g_err.c_str(); }
+
+int32_t d4_set_option(int32_t option, int32_t value) {
+    switch (option) {
+        case D4_OPT_GRAPHS:
+            if (value != 0 && value != 1) return fail(D4_EINVAL, "D4_OPT_GRAPHS takes 0 or 1, not %d", value);
+            g_opt_graphs.store(value);
+            return D4_OK;
+        case D4_OPT_ALIGNED_DRAWS:
+            if (value != 0 && value != 1) return fail(D4_EINVAL, "D4_OPT_ALIGNED_DRAWS takes 0 or 1, not %d", value);
+            g_opt_aligned_draws.store(value);
+            return D4_OK;
+        case D4_OPT_UPDATE_GRID:
+            if (value < 0 || value > 65535) return fail(D4_EINVAL, "D4_OPT_UPDATE_GRID %d outside 0..65535", value);
+            g_opt_update_grid.store(value);
+            return D4_OK;
+        default: return fail(D4_EINVAL, "unknown option %d", option);
+    }
+}
+
+int32_t d4_get_option(int32_t option, int32_t* value) {
+    if (!value) return fail(D4_EINVAL, "value is NULL");
+    switch (option) {
+        case D4_OPT_GRAPHS: *value = g_opt_graphs.load(); return D4_OK;
+        case D4_OPT_ALIGNED_DRAWS: *value = g_opt_aligned_draws.load(); return D4_OK;
+        case D4_OPT_UPDATE_GRID: *value = g_opt_update_grid.load(); return D4_OK;
+        default: return fail(D4_EINVAL, "unknown option %d", option);
+    }
+}
 
 int32_t d4_noise(const d4_problem* p, uint32_t iter, uint32_t step, float* eps, void* stream) {
     int rc = validate(p);
@@ -450,13 +515,13 @@ int32_t d4_denoise_iter(d4_ctx* c, const d4_problem* p, const float* x0, const f
     hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, st, c->iter, iter, c->status);
     HIP_LAUNCH_CHECK("k_set_iter");
     if (graphs_disabled()) {
-        rc = enqueue_iteration(c, st);
+        rc = enqueue_iteration(&c->prob, ctx_buffers(c), st);
         if (rc) return rc;
     } else {
         if (!c->captured) {
             HIP_TRY(hipStreamSynchronize(st));
             HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            rc = enqueue_iteration(c, c->cap_stream);
+            rc = enqueue_iteration(&c->prob, ctx_buffers(c), c->cap_stream);
             hipGraph_t g = nullptr;
             hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
             if (rc) {

@@ -299,8 +299,7 @@ int32_t d4_batch_iter(d4_batch* b, const float* x0_all, const float* goal_all, f
     HIP_LAUNCH_CHECK("k_fill_int");
     hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, st, b->iter, iter, b->status);
     HIP_LAUNCH_CHECK("k_set_iter");
-    const char* ng = std::getenv("D4_NO_GRAPH");
-    if (ng && ng[0] == '1') {
+    if (g_opt_graphs.load() == 0) {
         int rc = enqueue_batch_iteration(b, st);
         if (rc) return rc;
     } else {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -21,6 +22,14 @@ namespace d4host {
 using namespace d4;
 
 inline thread_local std::string g_err;
+
+// Process-wide launch options (d4_set_option): iterations replay a captured
+// graph; the whole-block draw window serves problems whose horizons start
+// every robot on a Philox block; the update kernel's grid follows its rule
+// (0) or a given workgroup count.
+inline std::atomic<int> g_opt_graphs{1};
+inline std::atomic<int> g_opt_aligned_draws{1};
+inline std::atomic<int> g_opt_update_grid{0};
 
 inline int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -243,24 +252,7 @@ inline Tile pick_tile(const d4_problem* p) {
     Tile o;
     if (tile_override(p->dyn, n, p->horizon, &o)) t = o;
     int S = t.S, Tb = t.Tb;
-    const char* env = std::getenv("D4_TILE_S");
-    if (env) {
-        int v = std::atoi(env);
-        if (v >= 1 && v <= 64 && v * n <= 256) S = v;
-    }
-    const char* envt = std::getenv("D4_TILE_TB");
-    if (envt) {
-        // the fused kernel walks a time block in whole draw chunks
-        const int cs = shape_of(p->dyn).du == 2 ? 2 : 4;
-        int v = std::atoi(envt);
-        if (v >= cs && v <= 64 && v % cs == 0) Tb = v;
-    }
     int R = t.R;
-    const char* envr = std::getenv("D4_TILE_R");
-    if (envr) {
-        int v = std::atoi(envr);
-        if (v >= 1 && v <= 16) R = v;
-    }
     if (R * S * n > 1024) R = std::max(1, 1024 / (S * n));
     Tile out;
     out.S = S;

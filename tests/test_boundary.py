@@ -123,3 +123,26 @@ def test_tile_rule_without_a_gpu():
         p, _, _ = bench.make_workload(name)
         assert AT.get_tile(p) == single, name
         assert AT.get_tile(p, batched=True) == batched, name
+
+
+def test_launch_options_without_a_gpu(L):
+    """Launch options are explicit calls of the C ABI (no environment
+    switches): defaults, round trip, and invalid options or values rejected."""
+    lib = L.lib()
+    v = ctypes.c_int32()
+    for name, default in (("graphs", 1), ("aligned_draws", 1), ("update_grid", 0)):
+        assert L.get_option(name) == default, name
+    with L.option("graphs", 0):
+        assert L.get_option("graphs") == 0
+    assert L.get_option("graphs") == 1
+    with L.option("update_grid", 256):
+        assert L.get_option("update_grid") == 256
+    assert L.get_option("update_grid") == 0
+    assert lib.d4_set_option(0, 2) == L.D4_EINVAL
+    assert lib.d4_set_option(1, -1) == L.D4_EINVAL
+    assert lib.d4_set_option(2, -5) == L.D4_EINVAL
+    assert lib.d4_set_option(9, 0) == L.D4_EINVAL
+    assert lib.d4_get_option(9, ctypes.byref(v)) == L.D4_EINVAL
+    assert lib.d4_get_option(0, None) == L.D4_EINVAL
+    assert L.get_option("graphs") == 1 and L.get_option("aligned_draws") == 1
+

@@ -5,8 +5,6 @@ Bars: normal draws and pair counts bit-exact; single RK4 steps within
 pairs sit inside the guard band of the threshold; the update within the FP32
 error of the softmax and reduction; final rewards within 1e-3 relative.
 """
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -230,18 +228,15 @@ def test_denoise_iteration_chain_and_graph(L):
     assert len(checks) == 9
     lo, hi = np.array(p.u_lo[:2], np.float32), np.array(p.u_hi[:2], np.float32)
     u_expect = np.minimum(np.maximum(u_base + _np(du0).reshape(u_base.shape), lo), hi)
-    for no_graph in ("1", "0"):
-        os.environ["D4_NO_GRAPH"] = no_graph
-        try:
+    for graphs in (0, 1):
+        with L.option("graphs", graphs):
             ctx = L.Context(p)
             u = _cu(u_base)
             traj = torch.empty((p.n_robots, p.horizon + 1, p.dx), dtype=torch.float32, device="cuda")
             st = ctx.denoise_iter(_cu(x0), _cu(g), u, kappa, traj=traj)
             ctx.close()
-        finally:
-            os.environ.pop("D4_NO_GRAPH", None)
         assert st["status"] == 0
-        assert np.array_equal(_np(u), u_expect), f"no_graph={no_graph}"
+        assert np.array_equal(_np(u), u_expect), f"graphs={graphs}"
         fin = ombd.apply_deformation(p, x0, g, u_base, _np(du0))
         assert abs(st["reward"] - fin["r"]) <= FINAL_RTOL * abs(fin["r"])
         assert st["hits"] == fin["hits"] and st["success"] == fin["success"]
@@ -334,13 +329,9 @@ def test_phase_free_and_general_draw_windows_agree(L):
     ub = _cu(_rand_controls(rng, p, 1, spread=0.5)[0].reshape(-1))
     du = _cu((rng.normal(size=p.D) * 0.3).astype(np.float32))
     outs = []
-    for flag in (None, "1"):
-        if flag:
-            os.environ["D4_NO_ALIGNED"] = flag
-        try:
+    for aligned in (1, 0):
+        with L.option("aligned_draws", aligned):
             outs.append([_np(t) for t in L.sample_rollout_fitness(p, _cu(x0), _cu(g), ub, du, 1, 33)])
-        finally:
-            os.environ.pop("D4_NO_ALIGNED", None)
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-6)
     assert np.array_equal(outs[0][2], outs[1][2])
