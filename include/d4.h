@@ -209,6 +209,22 @@ int32_t d4_denoise_iter(d4_ctx* ctx, const d4_problem* p, const float* x0, const
                         float* u_base, uint32_t iter, float* traj_out, d4_stats* stats,
                         void* stream);
 
+/*
+ * d4_denoise_iter for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels with the same results, but no d4_ctx, no graph and no
+ * allocation of any kind.  The workspace (draws, rewards, counts, the Delta U
+ * ping-pong, trajectory, stats, status) lives in one static device array of
+ * 64 MiB that every GPU the library runs on holds until the process ends:
+ * problems whose workspace (about 4 D M bytes plus small arrays) exceeds it
+ * return D4_EUNSUPPORTED before any launch.  Arguments as d4_denoise_iter;
+ * u_base is updated in place and x0, goal are read where they are.  Calls on
+ * one GPU share the array, so calls that overlap on one GPU (concurrent
+ * streams or threads) race; the array keeps the last call's contents.
+ */
+int32_t d4_denoise_iter_noalloc(const d4_problem* p, const float* x0, const float* goal, float* u_base,
+                                uint32_t iter, float* traj_out, d4_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------------
  * Launch-shape tuning of the reward kernels (d4_sample_rollout_fitness,
  * d4_fitness, d4_denoise_iter).  A tile is the number of samples per

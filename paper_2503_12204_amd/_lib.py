@@ -65,6 +65,7 @@ def _load():
         "d4_ctx_create": ([P, POINTER(c_void_p)], c_int32),
         "d4_ctx_destroy": ([c_void_p], c_int32),
         "d4_denoise_iter": ([c_void_p, P, fp, fp, fp, c_uint32, fp, POINTER(D4Stats), c_void_p], c_int32),
+        "d4_denoise_iter_noalloc": ([P, fp, fp, fp, c_uint32, fp, POINTER(D4Stats), c_void_p], c_int32),
         "d4_batch_create": ([P, c_int32, POINTER(c_void_p)], c_int32),
         "d4_batch_layout": ([c_void_p, fp, fp, fp, fp], c_int32),
         "d4_batch_iter": ([c_void_p, fp, fp, fp, c_uint32, POINTER(D4Stats), c_void_p], c_int32),
@@ -272,6 +273,20 @@ class Context:
         return dict(reward=s.reward, objective=s.objective, hits=s.hits, robots_hit=s.robots_hit,
                     success=bool(s.success), at_goal=bool(s.at_goal), obstacle_hits=s.obstacle_hits,
                     status=s.status)
+
+
+def denoise_iter_noalloc(p: Problem, x0, goal, u_base, iteration: int, traj=None):
+    """One iteration through d4_denoise_iter_noalloc (static workspace, no
+    allocation, no graph); u_base [n][T][d_u] is updated in place."""
+    c = to_c(p)
+    st = D4Stats()
+    tr = _dev(traj, (p.n_robots, p.horizon + 1, p.dx), name="traj") if traj is not None else None
+    _check(_lib.d4_denoise_iter_noalloc(ctypes.byref(c), _dev(x0, (p.n_robots, p.dx), name="x0"),
+                                        _dev(goal, (p.n_robots, p.dp), name="goal"),
+                                        _dev(u_base, (p.n_robots, p.horizon, p.du), name="u_base"), iteration, tr,
+                                        ctypes.byref(st), _stream()))
+    torch.cuda.current_stream().synchronize()
+    return _stats_dict(st)
 
 
 def plan(p: Problem, x0, goal, iterations: int, u_init=None, stop_on_success=False):

@@ -277,6 +277,40 @@ bool graphs_disabled() { return g_opt_graphs.load() == 0; }
 
 }  // namespace
 
+// ------------------------------------------ workspace of the allocation-free entry point
+// Every GPU the library runs on holds one copy of this array until the
+// process ends.  Host code never uses the array's name as an address: each
+// device's copy is reached through the pointer hipGetSymbolAddress returns
+// on that device (scratch_on_device).
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of the current device's scratch array, looked up once
+// per device with that device current.
+int scratch_on_device(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(D4_EUNSUPPORTED, "device %d beyond %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(D4_EHIP, "hipGetSymbolAddress of the static workspace failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return D4_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -539,6 +573,56 @@ int32_t d4_denoise_iter(d4_ctx* c, const d4_problem* p, const float* x0, const f
     if (traj_out)
         HIP_TRY(hipMemcpyAsync(traj_out, c->traj, 4 * n * (T + 1) * s.dx, hipMemcpyDeviceToDevice, st));
     if (stats) HIP_TRY(hipMemcpyAsync(stats, c->stats, sizeof(d4_stats), hipMemcpyDeviceToHost, st));
+    return D4_OK;
+}
+
+int32_t d4_denoise_iter_noalloc(const d4_problem* p, const float* x0, const float* goal, float* u_base,
+                                uint32_t iter, float* traj_out, d4_stats* stats, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    NEED(x0);
+    NEED(goal);
+    NEED(u_base);
+    if (traj_out) NEED(traj_out);
+    if (iter > 65535u) return fail(D4_EINVAL, "iter %u does not fit 16 bits", iter);
+    if (p->n_samples > 16384)
+        return fail(D4_EUNSUPPORTED, "n_samples %d above the 16384 weights one workgroup stages", p->n_samples);
+    const Shape s = shape_of(p->dyn);
+    const size_t n = p->n_robots, T = p->horizon, M = p->n_samples, D = n * T * s.du;
+    // workspace layout: eps [D][M], r [M], hits [M], Delta U ping-pong, trajectory, stats, status, iteration
+    const size_t o_eps = 0, o_r = o_eps + align256(4 * D * M), o_hits = o_r + align256(4 * M),
+                 o_dua = o_hits + align256(4 * M), o_dub = o_dua + align256(4 * D),
+                 o_traj = o_dub + align256(4 * D), o_stats = o_traj + align256(4 * n * (T + 1) * s.dx),
+                 o_status = o_stats + align256(sizeof(d4_stats)), o_iter = o_status + 256, total = o_iter + 256;
+    if (total > STATIC_SCRATCH_BYTES)
+        return fail(D4_EUNSUPPORTED, "problem needs %zu bytes of workspace, above the %zu of the static array", total,
+                    STATIC_SCRATCH_BYTES);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    unsigned char* base = nullptr;
+    rc = scratch_on_device(dev, &base);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    IterBuffers b;
+    b.x0 = x0;
+    b.goal = goal;
+    b.ubase = u_base;
+    b.eps = reinterpret_cast<float*>(base + o_eps);
+    b.r = reinterpret_cast<float*>(base + o_r);
+    b.hits = reinterpret_cast<int*>(base + o_hits);
+    b.du_a = reinterpret_cast<float*>(base + o_dua);
+    b.du_b = reinterpret_cast<float*>(base + o_dub);
+    b.traj = traj_out ? traj_out : reinterpret_cast<float*>(base + o_traj);
+    b.stats = reinterpret_cast<float*>(base + o_stats);
+    b.status = reinterpret_cast<int*>(base + o_status);
+    b.iter = reinterpret_cast<uint32_t*>(base + o_iter);
+    // the iteration index and the status word, written by a kernel (the
+    // previous call's values stay in the array)
+    hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, st, b.iter, iter, b.status);
+    HIP_LAUNCH_CHECK("k_set_iter");
+    rc = enqueue_iteration(p, b, st);
+    if (rc) return rc;
+    if (stats) HIP_TRY(hipMemcpyAsync(stats, b.stats, sizeof(d4_stats), hipMemcpyDeviceToHost, st));
     return D4_OK;
 }
 

@@ -146,3 +146,24 @@ def test_launch_options_without_a_gpu(L):
     assert lib.d4_get_option(0, None) == L.D4_EINVAL
     assert L.get_option("graphs") == 1 and L.get_option("aligned_draws") == 1
 
+
+def test_noalloc_entry_rejects_before_any_launch(L):
+    """The allocation-free iteration validates its arguments and its 64 MiB
+    workspace limit on the host: a problem whose draws alone exceed it fails
+    with D4_EUNSUPPORTED, NULL or misaligned pointers with D4_EINVAL."""
+    from paper_2503_12204_amd import workloads as W
+    lib = L.lib()
+    p, _, _ = W.holo3d_sphere()      # 16 x 100 x 3 x 8192 draws: 157 MB
+    c = L.to_c(p)
+    buf = (ctypes.c_float * 64)()
+    ptr = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.d4_denoise_iter_noalloc(ctypes.byref(c), ptr, ptr, ptr, 0, None, None, None) == L.D4_EUNSUPPORTED
+    assert "workspace" in lib.d4_last_error().decode()
+    q, _, _ = W.holo2d_circle()
+    cq = L.to_c(q)
+    assert lib.d4_denoise_iter_noalloc(ctypes.byref(cq), None, ptr, ptr, 0, None, None, None) == L.D4_EINVAL
+    odd = ctypes.c_void_p(ctypes.addressof(buf) + 2)
+    assert lib.d4_denoise_iter_noalloc(ctypes.byref(cq), ptr, ptr, odd, 0, None, None, None) == L.D4_EINVAL
+    assert lib.d4_denoise_iter_noalloc(ctypes.byref(cq), ptr, ptr, ptr, 70000, None, None, None) == L.D4_EINVAL
+    bad = L.to_c(q.replace(n_robots=0))
+    assert lib.d4_denoise_iter_noalloc(ctypes.byref(bad), ptr, ptr, ptr, 0, None, None, None) == L.D4_EINVAL
