@@ -287,8 +287,8 @@ def time_update_kernel(L, p, x0, g, u, iteration, reps=20):
 
 def time_update_kernel_cold(L, p, x0, g, u, iteration, reps=6):
     """Median duration of single update launches, each after 1 GiB of other
-    data has been written through the caches (HBM reads, no Infinity Cache
-    hits on the draws)."""
+    data has been read through the caches (HBM reads, no Infinity Cache hits
+    on the draws)."""
     import torch
     D, M = p.D, p.n_samples
     eps = torch.empty((D, M), dtype=torch.float32, device="cuda")
@@ -297,12 +297,13 @@ def time_update_kernel_cold(L, p, x0, g, u, iteration, reps=6):
     du = torch.zeros(D, dtype=torch.float32, device="cuda")
     du_out = torch.empty(D, dtype=torch.float32, device="cuda")
     w = torch.empty(M, dtype=torch.float32, device="cuda")
-    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    flush = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     L.sample_rollout_fitness(p, x0, g, u.reshape(-1).contiguous(), du, iteration, p.n_steps, eps, r, hits)
     s = torch.cuda.current_stream()
     times = []
     for k in range(reps):
-        flush.fill_(float(k))
+        # read 1 GiB of other data (reads leave no dirty lines to write back)
+        flush.sum()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
         L.score_update(p, r, eps, du, p.n_steps, du_out, w)
@@ -456,7 +457,7 @@ def main():
     # the weighted reduction: HBM-bound; algorithmic bytes = the draws read
     # once, the rewards, Delta U in and out, and the weights written once.
     # In the iteration the draws come straight from the fused kernel and part
-    # of them from the 256 MB Infinity Cache; the cold figure first streams
+    # of them from the 256 MB Infinity Cache; the cold figure first reads
     # 1 GiB of other data through the caches before each timed launch.
     t_u = time_update_kernel(L, p, x0, g, u, args.warmup + args.steps + 2)
     t_uc = time_update_kernel_cold(L, p, x0, g, u, args.warmup + args.steps + 2)

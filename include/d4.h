@@ -120,9 +120,15 @@ const char* d4_last_error(void);
  *  D4_OPT_UPDATE_GRID   0 (default): the update kernel's grid follows its rule
  *                       (at most 512 workgroups of two rows each); n > 0: n
  *                       workgroups (capped at D).
+ *  D4_OPT_BATCH_PERSISTENT 0 (default): d4_batch_iter runs each denoising step
+ *                       as one reward launch and one update launch; 1 would run
+ *                       it as one persistent launch over a work list of reward
+ *                       and update tiles, but that form is switched off in this
+ *                       build (it did not finish on the GPU): setting 1 returns
+ *                       D4_EUNSUPPORTED.
  * d4_set_option returns D4_EINVAL for an unknown option or a value outside the
  * ranges above; d4_get_option writes the current value to *value (host). */
-enum { D4_OPT_GRAPHS = 0, D4_OPT_ALIGNED_DRAWS = 1, D4_OPT_UPDATE_GRID = 2 };
+enum { D4_OPT_GRAPHS = 0, D4_OPT_ALIGNED_DRAWS = 1, D4_OPT_UPDATE_GRID = 2, D4_OPT_BATCH_PERSISTENT = 3 };
 int32_t d4_set_option(int32_t option, int32_t value);
 int32_t d4_get_option(int32_t option, int32_t* value);
 
@@ -267,11 +273,13 @@ int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int
  * Algorithm 1), with its own team size, horizon, dynamics, limits, start and
  * goal; every instance must share n_samples, n_steps, temperature,
  * beta_min/beta_max, flags and seed (instance_id tells their draws apart).
- * One reward launch over all (instance, sample block) tiles, longest first,
- * and one update launch over all (instance, row range) tiles per denoising
- * step; the iteration replays one captured HIP graph.  With the default
- * launch shapes an instance's results equal its own d4_denoise_iter run
- * bit for bit.
+ * Each denoising step is one reward launch over all (instance, sample block)
+ * tiles, longest first, and one update launch over all (instance, row range)
+ * tiles; the iteration replays one captured HIP graph.  (A persistent form,
+ * one launch per step taking reward and update tiles from the work list of
+ * d4_batch_work_list, is built but switched off: see D4_OPT_BATCH_PERSISTENT.)
+ * With the default launch shapes an instance's results equal its own
+ * d4_denoise_iter run bit for bit.
  * ------------------------------------------------------------------------ */
 typedef struct d4_batch d4_batch;
 
@@ -295,6 +303,17 @@ int32_t d4_batch_iter(d4_batch* batch, const float* x0_all, const float* goal_al
                       uint32_t iter, d4_stats* stats, void* stream);
 
 int32_t d4_batch_destroy(d4_batch* batch);
+
+/* The work list of the persistent step for these problems, computed on the
+ * host (no GPU call), as d4_batch_create builds it with lag = the launch's
+ * workgroup count: items (host, [capacity][4]) receives (kind, instance, a, b)
+ * per item in list order, kind 0 a reward tile of samples a .. a+S-1, kind 1
+ * an update tile of rows a .. b-1; *n_items (host) the list length.
+ * D4_EINVAL if the list needs more than `capacity` items (n_items still set).
+ * Every reward tile of an instance precedes every update tile of it, which
+ * is what bounds the persistent kernel's waits; the CPU tests check that. */
+int32_t d4_batch_work_list(const d4_problem* probs, int32_t count, int32_t lag, int32_t capacity, int32_t* items,
+                           int32_t* n_items);
 
 /* ------------------------------------------------------------------------
  * Learned proposal: a permutation-equivariant set network that predicts the

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libd4.so")
 
 D4_OK, D4_EINVAL, D4_ENOMEM, D4_EHIP, D4_ENONFINITE, D4_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MAX_OBSTACLES = 16
-OPTIONS = {"graphs": 0, "aligned_draws": 1, "update_grid": 2}
+OPTIONS = {"graphs": 0, "aligned_draws": 1, "update_grid": 2, "batch_persistent": 3}
 
 
 class D4Error(RuntimeError):
@@ -70,6 +70,7 @@ def _load():
         "d4_batch_layout": ([c_void_p, fp, fp, fp, fp], c_int32),
         "d4_batch_iter": ([c_void_p, fp, fp, fp, c_uint32, POINTER(D4Stats), c_void_p], c_int32),
         "d4_batch_destroy": ([c_void_p], c_int32),
+        "d4_batch_work_list": ([P, c_int32, c_int32, c_int32, fp, fp], c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -306,6 +307,18 @@ def plan(p: Problem, x0, goal, iterations: int, u_init=None, stop_on_success=Fal
     finally:
         ctx.close()
     return u, hist
+
+
+def batch_work_list(probs, lag):
+    """The persistent step's work list for these problems (host only):
+    int32 array [items][4] of (kind, instance, a, b)."""
+    import numpy as np
+    arr = (D4Problem * len(probs))(*[to_c(p) for p in probs])
+    n = c_int32()
+    _lib.d4_batch_work_list(arr, len(probs), int(lag), 0, None, ctypes.byref(n))
+    out = np.zeros((max(n.value, 1), 4), dtype=np.int32)
+    _check(_lib.d4_batch_work_list(arr, len(probs), int(lag), n.value, c_void_p(out.ctypes.data), ctypes.byref(n)))
+    return out[:n.value]
 
 
 def _stats_dict(s):

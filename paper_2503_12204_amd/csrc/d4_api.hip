@@ -330,6 +330,13 @@ int32_t d4_set_option(int32_t option, int32_t value) {
             if (value < 0 || value > 65535) return fail(D4_EINVAL, "D4_OPT_UPDATE_GRID %d outside 0..65535", value);
             g_opt_update_grid.store(value);
             return D4_OK;
+        case D4_OPT_BATCH_PERSISTENT:
+            if (value != 0 && value != 1) return fail(D4_EINVAL, "D4_OPT_BATCH_PERSISTENT takes 0 or 1, not %d", value);
+            // the persistent step did not finish on the GPU and is switched off
+            // until the cause is found (the two-launch form serves every batch)
+            if (value == 1) return fail(D4_EUNSUPPORTED, "the persistent batched step is switched off in this build");
+            g_opt_batch_persistent.store(value);
+            return D4_OK;
         default: return fail(D4_EINVAL, "unknown option %d", option);
     }
 }
@@ -340,6 +347,7 @@ int32_t d4_get_option(int32_t option, int32_t* value) {
         case D4_OPT_GRAPHS: *value = g_opt_graphs.load(); return D4_OK;
         case D4_OPT_ALIGNED_DRAWS: *value = g_opt_aligned_draws.load(); return D4_OK;
         case D4_OPT_UPDATE_GRID: *value = g_opt_update_grid.load(); return D4_OK;
+        case D4_OPT_BATCH_PERSISTENT: *value = g_opt_batch_persistent.load(); return D4_OK;
         default: return fail(D4_EINVAL, "unknown option %d", option);
     }
 }

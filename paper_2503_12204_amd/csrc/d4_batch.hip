@@ -1,7 +1,9 @@
 // Host side of the batched form: many independent planning problems of
-// uneven team size, horizon and dynamics advanced together, one reward launch
-// and one update launch per denoising step over all instances, one graph per
-// iteration.
+// uneven team size, horizon and dynamics advanced together, one graph per
+// iteration.  Each denoising step is one reward launch and one update launch.
+// The persistent form (one launch per step over a work list of reward and
+// update tiles, k_batch_persist) is built but switched off: it did not
+// finish on the GPU, and d4_set_option refuses to select it.
 #include "d4.h"
 #include "d4_host.hpp"
 
@@ -24,6 +26,13 @@ struct d4_batch {
     float *x0, *goal, *u, *du_a, *du_b, *eps, *r, *traj, *stats;
     int *hits, *status;
     uint32_t* iter;
+    // persistent step: work list, reward tiles per instance, two counter sets
+    std::vector<BatchWork> work;
+    BatchWork* d_work;
+    int* d_tiles_of;
+    int* d_cnt;
+    int persist_grid;
+    int captured_form;
     bool captured;
     hipStream_t cap_stream;
     hipGraph_t graph;
@@ -50,12 +59,60 @@ double tile_cost(const d4_problem& p) {
 void free_batch(d4_batch* b) {
     void* ptrs[] = {b->d_insts, b->d_tiles, b->d_rows, b->x0,     b->goal,  b->u,      b->du_a,
                     b->du_b,    b->eps,     b->r,      b->traj,   b->stats, b->hits,   b->status,
-                    b->iter};
+                    b->iter,    b->d_work,  b->d_tiles_of, b->d_cnt};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
 
 constexpr int ROWS_PER_TILE = 64;
+
+// Polls of an update tile's wait before the persistent step gives up on it:
+// each poll is one device-scope load (about a microsecond) and a sleep of
+// about 512 cycles, some 0.1 s in all, against reward tiles of well under a
+// millisecond.
+constexpr int SPIN_LIMIT = 1 << 16;
+
+struct InstPlan {
+    int S, D;
+    double cost;
+};
+
+// Work list of the persistent step.  Instances in descending tile cost; the
+// reward tiles of each instance in turn; the update tiles of instance j
+// follow once `lag` further reward tiles have been listed after its last one
+// (by the time a workgroup takes them, instance j's tiles have most likely
+// finished, and its draws are still in the Infinity Cache), and the update
+// tiles still pending close the list.  Every reward tile of an instance
+// precedes every update tile of it.
+std::vector<BatchWork> batch_work_list(const std::vector<InstPlan>& ip, int M, int lag) {
+    const int count = (int)ip.size();
+    std::vector<int> order(count);
+    for (int j = 0; j < count; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ip[x].cost > ip[y].cost; });
+    std::vector<BatchWork> out;
+    std::vector<std::pair<long long, int>> pending;  // (reward tiles listed when j's last one was, j)
+    size_t head = 0;
+    long long rewards = 0;
+    auto emit_updates = [&](int j) {
+        for (int e0 = 0; e0 < ip[j].D; e0 += ROWS_PER_TILE)
+            out.push_back(BatchWork{1, j, e0, std::min(ip[j].D, e0 + ROWS_PER_TILE)});
+    };
+    for (int j : order) {
+        for (int m0 = 0; m0 < M; m0 += ip[j].S) {
+            out.push_back(BatchWork{0, j, m0, 0});
+            ++rewards;
+            while (head < pending.size() && pending[head].first + lag <= rewards) emit_updates(pending[head++].second);
+        }
+        pending.push_back({rewards, j});
+    }
+    while (head < pending.size()) emit_updates(pending[head++].second);
+    return out;
+}
+
+InstPlan plan_of(const d4_problem& p) {
+    const Tile t = default_tile(p.dyn, p.n_robots);
+    return InstPlan{t.S, p.n_robots * p.horizon * shape_of(p.dyn).du, tile_cost(p)};
+}
 
 int enqueue_batch_iteration(d4_batch* b, hipStream_t st) {
     const d4_problem& p0 = b->probs[0];
@@ -92,20 +149,53 @@ int enqueue_batch_iteration(d4_batch* b, hipStream_t st) {
     ua.inv_lam = 1.0f / p0.temperature;
     ua.normalize = (p0.flags & FLAG_NORMALIZE) ? 1 : 0;
     allow_lds(k_batch_rollfit, b->lds_rollfit);
+    const bool persist = g_opt_batch_persistent.load() != 0;
+    const int J = upd_reg_j(M, b->eps, b->r);
+    const int cnt_stride = CNT_DONE + b->count;
+    if (persist) {
+        // both counter sets start from zero (a kernel, not a memset, so that
+        // the captured graph holds no memset node)
+        hipLaunchKernelGGL(k_fill_int, dim3((2 * cnt_stride + 255) / 256), dim3(256), 0, st, b->d_cnt,
+                           2 * cnt_stride, 0);
+        HIP_LAUNCH_CHECK("k_fill_int");
+    }
     for (int i = p0.n_steps; i >= 1; --i) {
         a.du_in = du_cur;
         a.step = (uint32_t)i;
         a.mean_scale = sc.ms[i];
         a.sigma = sc.sigma[i];
-        hipLaunchKernelGGL(k_batch_rollfit, dim3((unsigned)b->tiles.size()), dim3(256), b->lds_rollfit, st, a);
-        HIP_LAUNCH_CHECK("k_batch_rollfit");
         ua.du_in = du_cur;
         ua.du_out = du_nxt;
         ua.ms = sc.ms[i];
         ua.sigma = sc.sigma[i];
         ua.os = sc.os[i];
+        if (persist) {
+            BatchPersistArgs pa;
+            pa.s = a;
+            pa.u = ua;
+            pa.work = b->d_work;
+            pa.tiles_of = b->d_tiles_of;
+            pa.cnt = b->d_cnt + (i & 1) * cnt_stride;
+            pa.n_work = (int)b->work.size();
+            pa.count = b->count;
+            pa.spin_limit = SPIN_LIMIT;
+            const dim3 g((unsigned)b->persist_grid);
+            switch (J) {
+                case 0: hipLaunchKernelGGL(k_batch_persist<0>, g, dim3(256), b->lds_rollfit, st, pa); break;
+                case 1: hipLaunchKernelGGL(k_batch_persist<1>, g, dim3(256), b->lds_rollfit, st, pa); break;
+                case 2: hipLaunchKernelGGL(k_batch_persist<2>, g, dim3(256), b->lds_rollfit, st, pa); break;
+                case 4: hipLaunchKernelGGL(k_batch_persist<4>, g, dim3(256), b->lds_rollfit, st, pa); break;
+                case 8: hipLaunchKernelGGL(k_batch_persist<8>, g, dim3(256), b->lds_rollfit, st, pa); break;
+                default: hipLaunchKernelGGL(k_batch_persist<16>, g, dim3(256), b->lds_rollfit, st, pa); break;
+            }
+            HIP_LAUNCH_CHECK("k_batch_persist");
+            std::swap(du_cur, du_nxt);
+            continue;
+        }
+        hipLaunchKernelGGL(k_batch_rollfit, dim3((unsigned)b->tiles.size()), dim3(256), b->lds_rollfit, st, a);
+        HIP_LAUNCH_CHECK("k_batch_rollfit");
         const dim3 ng((unsigned)b->rows.size());
-        switch (upd_reg_j(M, b->eps, b->r)) {
+        switch (J) {
             case 0: hipLaunchKernelGGL(k_batch_update<0>, ng, dim3(256), (size_t)M * 4, st, ua); break;
             case 1: hipLaunchKernelGGL(k_batch_update<1>, ng, dim3(256), 0, st, ua); break;
             case 2: hipLaunchKernelGGL(k_batch_update<2>, ng, dim3(256), 0, st, ua); break;
@@ -117,6 +207,8 @@ int enqueue_batch_iteration(d4_batch* b, hipStream_t st) {
         std::swap(du_cur, du_nxt);
     }
     BatchFinalArgs f;
+    f.wait_error = persist ? b->d_cnt + CNT_ERROR : nullptr;
+    f.cnt_stride = cnt_stride;
     f.insts = b->d_insts;
     f.u = b->u;
     f.du0 = du_cur;
@@ -245,12 +337,41 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
         {(void**)&b->stats, sizeof(d4_stats) * (size_t)count},
         {(void**)&b->status, 4 * (size_t)count},
         {(void**)&b->iter, 4},
+        {(void**)&b->d_tiles_of, 4 * (size_t)count},
+        {(void**)&b->d_cnt, 4 * 2 * (size_t)(CNT_DONE + count)},
     };
     for (auto& a : allocs) {
         if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
             free_batch(b);
             delete b;
             return fail(D4_ENOMEM, "hipMalloc of %zu bytes failed", a.bytes);
+        }
+    }
+    // persistent step: occupancy-sized grid, work list, per-instance tile counts
+    {
+        std::vector<InstPlan> ip;
+        std::vector<int> tiles_of;
+        for (int j = 0; j < count; ++j) {
+            ip.push_back(plan_of(probs[j]));
+            tiles_of.push_back((int)((M + ip.back().S - 1) / ip.back().S));
+        }
+        int cus = 0, per_cu = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+        allow_lds(k_batch_persist<1>, b->lds_rollfit);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_batch_persist<1>),
+                                                         256, b->lds_rollfit) != hipSuccess)
+            per_cu = 1;
+        b->persist_grid = std::max(1, std::max(1, per_cu) * std::max(1, cus));
+        b->work = batch_work_list(ip, (int)M, b->persist_grid);
+        b->persist_grid = std::min<int>(b->persist_grid, (int)b->work.size());
+        if (hipMalloc(&b->d_work, sizeof(BatchWork) * b->work.size()) != hipSuccess ||
+            hipMemcpy(b->d_work, b->work.data(), sizeof(BatchWork) * b->work.size(), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(b->d_tiles_of, tiles_of.data(), 4 * (size_t)count, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(b->d_cnt, 0, 4 * 2 * (size_t)(CNT_DONE + count)) != hipSuccess) {
+            free_batch(b);
+            delete b;
+            return fail(D4_ENOMEM, "persistent-step work list set-up failed");
         }
     }
     hipError_t e1 = hipMemcpy(b->d_insts, b->insts.data(), sizeof(BatchInst) * b->insts.size(), hipMemcpyHostToDevice);
@@ -299,11 +420,20 @@ int32_t d4_batch_iter(d4_batch* b, const float* x0_all, const float* goal_all, f
     HIP_LAUNCH_CHECK("k_fill_int");
     hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, st, b->iter, iter, b->status);
     HIP_LAUNCH_CHECK("k_set_iter");
+    const int form = g_opt_batch_persistent.load();
+    if (b->captured && b->captured_form != form) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->captured = false;
+    }
     if (g_opt_graphs.load() == 0) {
         int rc = enqueue_batch_iteration(b, st);
         if (rc) return rc;
     } else {
         if (!b->captured) {
+            b->captured_form = form;
             HIP_TRY(hipStreamSynchronize(st));
             HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
             int rc = enqueue_batch_iteration(b, b->cap_stream);
@@ -323,6 +453,31 @@ int32_t d4_batch_iter(d4_batch* b, const float* x0_all, const float* goal_all, f
     HIP_TRY(hipMemcpyAsync(u_all, b->u, 4 * (size_t)b->tot_u, hipMemcpyDeviceToDevice, st));
     if (stats)
         HIP_TRY(hipMemcpyAsync(stats, b->stats, sizeof(d4_stats) * (size_t)b->count, hipMemcpyDeviceToHost, st));
+    return D4_OK;
+}
+
+int32_t d4_batch_work_list(const d4_problem* probs, int32_t count, int32_t lag, int32_t capacity, int32_t* items,
+                           int32_t* n_items) {
+    if (!probs || count < 1) return fail(D4_EINVAL, "need at least one problem");
+    if (lag < 0 || capacity < 0 || !n_items || (capacity > 0 && !items))
+        return fail(D4_EINVAL, "bad lag, capacity or output");
+    std::vector<InstPlan> ip;
+    for (int j = 0; j < count; ++j) {
+        int rc = validate(&probs[j]);
+        if (rc) return fail(rc, "instance %d: %s", j, g_err.c_str());
+        if (!same_sampler(probs[j], probs[0]))
+            return fail(D4_EINVAL, "instance %d: sampler settings differ from instance 0", j);
+        ip.push_back(plan_of(probs[j]));
+    }
+    const std::vector<BatchWork> w = batch_work_list(ip, probs[0].n_samples, lag);
+    *n_items = (int32_t)w.size();
+    if ((int64_t)w.size() > capacity) return fail(D4_EINVAL, "work list of %zu items exceeds capacity %d", w.size(), capacity);
+    for (size_t i = 0; i < w.size(); ++i) {
+        items[4 * i] = w[i].kind;
+        items[4 * i + 1] = w[i].inst;
+        items[4 * i + 2] = w[i].a;
+        items[4 * i + 3] = w[i].b;
+    }
     return D4_OK;
 }
 

@@ -30,6 +30,7 @@ inline thread_local std::string g_err;
 inline std::atomic<int> g_opt_graphs{1};
 inline std::atomic<int> g_opt_aligned_draws{1};
 inline std::atomic<int> g_opt_update_grid{0};
+inline std::atomic<int> g_opt_batch_persistent{0};
 
 inline int fail(int code, const char* fmt, ...) {
     char buf[512];

@@ -820,8 +820,13 @@ static __global__ void __launch_bounds__(256) k_softmax_update(const UpdateArgs 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 // Range-checked 16-byte buffer load: bytes past num_records read as zero.
+// AUX is the cache policy: 0 the default, CPOL_AGENT a load coherent at
+// device scope (sc1), which reads what other workgroups of the same launch
+// published with a device-scope release, whichever XCD's L2 they wrote through.
+constexpr int CPOL_AGENT = 16;
+template <int AUX = 0>
 __device__ __forceinline__ f4v load4_checked(__amdgpu_buffer_rsrc_t rs, int byte_offset) {
-    return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_offset, 0, 0));
+    return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_offset, 0, AUX));
 }
 
 // The same update for a sample count that is a multiple of 4, with the
@@ -853,7 +858,7 @@ __device__ __forceinline__ float block_max4(float s, float* red) {
     return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
-template <int J>
+template <int J, int AUX = 0>
 __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0, int e1, bool first) {
 #pragma clang fp contract(off)
     __shared__ float red[4];
@@ -864,7 +869,7 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
         __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.r), (short)0, M * 4, 0x00020000);
     f4v w[J];
 #pragma unroll
-    for (int j = 0; j < J; ++j) w[j] = load4_checked(r_rs, (tid + 256 * j) * 16);
+    for (int j = 0; j < J; ++j) w[j] = load4_checked<AUX>(r_rs, (tid + 256 * j) * 16);
     f4v x[UPD_ROWS][J];
     auto load_rows = [&](int e) {
 #pragma unroll
@@ -873,7 +878,7 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<float*>(a.eps + (size_t)ee * M), (short)0, M * 4, 0x00020000);
 #pragma unroll
-            for (int j = 0; j < J; ++j) x[q][j] = load4_checked(rs, (tid + 256 * j) * 16);
+            for (int j = 0; j < J; ++j) x[q][j] = load4_checked<AUX>(rs, (tid + 256 * j) * 16);
         }
     };
     if (e0 < e1) load_rows(e0);
@@ -1154,10 +1159,10 @@ struct BatchStepArgs {
     float mean_scale, sigma;
 };
 
-// Sampling + rollout + reward of one tile per workgroup (256 lanes).
-static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArgs b) {
-    extern __shared__ float lds[];
-    const BatchTile tl = b.tiles[blockIdx.x];
+// Sampling + rollout + reward of samples m0 .. m0+S-1 of instance inst (one
+// 256-lane workgroup).
+__device__ __forceinline__ void batch_reward_tile(const BatchStepArgs& b, int inst, int m0, float* lds) {
+    const BatchTile tl{inst, m0};
     const BatchInst& in = b.insts[tl.inst];
     RollFitArgs a;
     a.x0 = b.x0 + in.x0;
@@ -1214,6 +1219,13 @@ static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArg
     }
 }
 
+// One reward tile per workgroup, from the launch's tile list.
+static __global__ void __launch_bounds__(256) k_batch_rollfit(const BatchStepArgs b) {
+    extern __shared__ float lds[];
+    const BatchTile tl = b.tiles[blockIdx.x];
+    batch_reward_tile(b, tl.inst, tl.m0, lds);
+}
+
 struct BatchUpdArgs {
     const BatchInst* insts;
     const BatchRows* rows;
@@ -1228,12 +1240,12 @@ struct BatchUpdArgs {
     float ms, sigma, os;
 };
 
-// Softmax weights and the update of one row range per workgroup: the
-// register form (J > 0, sample count a multiple of 4) or the LDS form (J = 0).
-template <int J>
-__global__ void __launch_bounds__(256) k_batch_update(const BatchUpdArgs b) {
-    extern __shared__ float wl[];
-    const BatchRows rt = b.rows[blockIdx.x];
+// Softmax weights and the update of rows e0 .. e1-1 of instance inst (one
+// 256-lane workgroup): the register form (J > 0, sample count a multiple of
+// 4) or the LDS form (J = 0, weights staged in wl).
+template <int J, int AUX = 0>
+__device__ __forceinline__ void batch_update_tile(const BatchUpdArgs& b, int inst, int e0, int e1, float* wl) {
+    const BatchRows rt{inst, e0, e1};
     const BatchInst& in = b.insts[rt.inst];
     UpdateArgs a;
     a.eps = b.eps + in.eps;
@@ -1250,12 +1262,115 @@ __global__ void __launch_bounds__(256) k_batch_update(const BatchUpdArgs b) {
     a.sigma = b.sigma;
     a.os = b.os;
     if constexpr (J > 0)
-        softmax_update_block<J>(a, rt.e0, rt.e1, rt.e0 == 0);
+        softmax_update_block<J, AUX>(a, rt.e0, rt.e1, rt.e0 == 0);
     else
         softmax_update_rows(a, rt.e0, blockDim.x >> 6, rt.e1, rt.e0 == 0, wl);
 }
 
+// One row range per workgroup, from the launch's row list.
+template <int J>
+__global__ void __launch_bounds__(256) k_batch_update(const BatchUpdArgs b) {
+    extern __shared__ float wl[];
+    const BatchRows rt = b.rows[blockIdx.x];
+    batch_update_tile<J>(b, rt.inst, rt.e0, rt.e1, wl);
+}
+
+// ----------------------------------------------- persistent batched step
+// Work item of the persistent step kernel: a reward tile (kind 0: samples
+// a .. a+S-1 of instance inst) or an update tile (kind 1: rows a .. b-1).
+struct BatchWork {
+    int kind, inst, a, b;
+};
+
+// Per-step counters of the persistent kernel (ints): the next work item, the
+// workgroups that have left, a wait-timeout flag, then per instance the
+// number of its reward tiles completed.
+enum { CNT_NEXT = 0, CNT_EXIT = 1, CNT_ERROR = 2, CNT_DONE = 3 };
+
+struct BatchPersistArgs {
+    BatchStepArgs s;
+    BatchUpdArgs u;
+    const BatchWork* work;
+    const int* tiles_of;   // [count] reward tiles per instance
+    int* cnt;              // this step's counter set: CNT_DONE + count ints
+    int n_work, count, spin_limit;
+};
+
+// One denoising step of every instance in one launch.  Workgroups take work
+// items in list order from an atomic counter.  A reward tile publishes its
+// draws, rewards and counts with a device-scope release (each wave writes
+// its stores back past its XCD's L2, then one lane counts the tile done for
+// its instance); an update tile first waits until every reward tile of its
+// instance is done, polling the count with relaxed device-scope loads (no
+// cache invalidation per poll), and then reads the instance's rewards and
+// draws with device-coherent (sc1) loads; the LDS form of the update, for
+// sample counts that are not a multiple of 4, takes a device-scope acquire
+// instead.  The list puts every reward tile of an instance before any of its
+// update tiles, so an update tile only waits on reward tiles that running
+// workgroups already hold: the wait always ends.  It is bounded all the same:
+// past spin_limit polls, or once any workgroup has timed out, the workgroup
+// sets the error flag, skips the tile and goes on, so every workgroup exits.
+// The last workgroup to leave clears the counter set for its next use.
+template <int J>
+__global__ void __launch_bounds__(256) k_batch_persist(const BatchPersistArgs p) {
+    extern __shared__ float lds[];
+    __shared__ int s_item, s_ok;
+    int* const done = p.cnt + CNT_DONE;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&p.cnt[CNT_NEXT], 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= p.n_work) break;
+        const BatchWork w = p.work[it];
+        if (w.kind == 0) {
+            batch_reward_tile(p.s, w.inst, w.a, lds);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[w.inst], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (threadIdx.x == 0) {
+                const int need = p.tiles_of[w.inst];
+                int spins = 0, ok = 1;
+                while (__hip_atomic_load(&done[w.inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (++spins > p.spin_limit ||
+                        __hip_atomic_load(&p.cnt[CNT_ERROR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        ok = 0;
+                        atomicExch(&p.cnt[CNT_ERROR], 1);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (s_ok) {
+                if constexpr (J > 0) {
+                    batch_update_tile<J, CPOL_AGENT>(p.u, w.inst, w.a, w.b, lds);
+                } else {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    batch_update_tile<0>(p.u, w.inst, w.a, w.b, lds);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __shared__ int s_last;
+    if (threadIdx.x == 0) s_last = atomicAdd(&p.cnt[CNT_EXIT], 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        for (int j = threadIdx.x; j < p.count; j += blockDim.x) done[j] = 0;
+        if (threadIdx.x == 0) {
+            p.cnt[CNT_NEXT] = 0;
+            p.cnt[CNT_EXIT] = 0;
+        }
+    }
+}
+
 struct BatchFinalArgs {
+    const int* wait_error;   // two counter sets' error flags (CNT_ERROR of each), or null
+    int cnt_stride;
     const BatchInst* insts;
     float* u;
     const float* du0;
@@ -1300,6 +1415,10 @@ static __global__ void __launch_bounds__(256) k_batch_final(const BatchFinalArgs
         case UNICYCLE: apply_final_body<UNICYCLE>(a); break;
         default: apply_final_body<DIFFDRIVE>(a); break;
     }
+    // a persistent step whose wait timed out skipped update tiles: every
+    // instance reports it (the stats' status word, thread 0 wrote it above)
+    if (threadIdx.x == 0 && b.wait_error && (b.wait_error[0] | b.wait_error[b.cnt_stride]))
+        reinterpret_cast<int*>(a.stats)[7] = -3;
 }
 
 static __global__ void k_fill_int(int* p, int n, int v) {

@@ -145,6 +145,10 @@ def test_launch_options_without_a_gpu(L):
     assert lib.d4_get_option(9, ctypes.byref(v)) == L.D4_EINVAL
     assert lib.d4_get_option(0, None) == L.D4_EINVAL
     assert L.get_option("graphs") == 1 and L.get_option("aligned_draws") == 1
+    # the persistent batched step is switched off: the two-launch form is the default and stays
+    assert L.get_option("batch_persistent") == 0
+    assert lib.d4_set_option(3, 1) == L.D4_EUNSUPPORTED
+    assert lib.d4_set_option(3, 0) == L.D4_OK
 
 
 def test_noalloc_entry_rejects_before_any_launch(L):

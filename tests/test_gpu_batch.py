@@ -181,3 +181,32 @@ def test_batch_largest_instance_against_oracle(L, dyn):
     finally:
         AT.clear_tile(p.dyn, p.n_robots, p.horizon)
     assert np.array_equal(u.cpu().numpy(), got) and hist[0] == stats[0]
+
+
+@pytest.mark.skip(reason="the persistent batched step did not finish on the GPU (twice, in the first batch "
+                         "test, 10 instances, M = 160); the cause is not found and the form is switched off "
+                         "(d4_set_option refuses it)")
+def test_persistent_step_equals_two_launch_form(L):
+    """The persistent step (one launch per denoising step over the work list)
+    and the two-launch form (reward launch, update launch) run the same
+    arithmetic on the same tiles: identical plans and statistics, graph or
+    no graph, and no wait timed out (status 0)."""
+    inst = _mix(20, 256, 8, seed=11, t_range=(9, 70))
+    q, x0q, gq = W.diffdrive_circle(n=7, horizon=31, n_samples=256)
+    inst.append((q.replace(n_steps=8, instance_id=30), x0q, gq))
+    probs = [p for p, _, _ in inst]
+    print("case persistent vs two-launch", len(probs), "instances", flush=True)
+    res = {}
+    for persistent in (1, 0):
+        for graphs in (1, 0):
+            with L.option("batch_persistent", persistent), L.option("graphs", graphs):
+                bc = L.BatchContext(probs, [x for _, x, _ in inst], [g for _, _, g in inst])
+                for it in range(2):
+                    stats = bc.iterate(it)
+                res[(persistent, graphs)] = (bc.u.cpu().numpy(), stats)
+                bc.close()
+    ref_u, ref_st = res[(0, 1)]
+    assert all(s["status"] == 0 for s in ref_st)
+    for key, (u, st) in res.items():
+        assert np.array_equal(u, ref_u), key
+        assert st == ref_st, key
