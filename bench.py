@@ -108,11 +108,8 @@ def ops_per_unit(dyn, n, steps_per_block, n_obstacles=0):
 # avoids most pair checks and earns that as speed.  At 16 robots in 3D:
 # 120 + 9 + 15 + 8 + 60 = 212.
 def algorithmic_ops(dyn, n, n_obstacles=0):
-    from paper_2503_12204_amd import workloads as W
-    dx, du, dp = W.dims(dyn)
-    dynamics = 80.0 if dyn in (W.UNICYCLE, W.DIFFDRIVE) else 5.0 * dp
-    check = 2.0 * dp + 2.0
-    return 40.0 * du + 3.0 * du + dynamics + 8.0 + (n - 1) / 2.0 * check + n_obstacles * check
+    from paper_2503_12204_amd import experiments as E
+    return E.algorithmic_ops(dyn, n, n_obstacles)
 
 
 def issue_seconds_per_unit(ops):
@@ -325,10 +322,15 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="only launch the fused kernel this many times (for counter runs)")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
-    ap.add_argument("--experiment", choices=["batched", "proposal", "sensitivity", "first_success"], default=None,
+    ap.add_argument("--experiment", choices=["batched", "proposal", "sensitivity", "first_success", "gemm"],
+                    default=None,
                     help="time-to-target of the batched or learned-proposal form against the plain planner, "
                          "or the success-rate sweep over denoising steps and iterations")
     ap.add_argument("--runs", type=int, default=30, help="runs per cell of the sensitivity sweep")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched experiment: time the batched form only (for profiling runs)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched experiment: keep the rule's tiles (no bucket autotuning)")
     ap.add_argument("--radius", type=float, default=None,
                     help="circle (sphere) radius, m: 2 for the sensitivity sweep, 4 for first_success by default")
     ap.add_argument("--dynamics", default="diffdrive,holo2d,holo3d", help="dynamics of the sensitivity sweep")
@@ -357,12 +359,24 @@ def main():
             print(msg, file=sys.stderr, flush=True)
 
         if args.experiment == "batched":
-            res = E.batched_vs_plain(L, log=log)
+            res = E.batched_vs_plain(L, plain=not args.no_plain, tune=not args.no_tune, log=log)
             out = {"metric": "time-to-target speedup of the batched form over the plain planner",
-                   "value": res["speedup"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
+                   "value": res.get("speedup"), "unit": "x", "n_gpus": 1, "higher_is_better": True,
                    "dtype": "f32", "data": "synthetic",
                    "config": {"workload": "batched_mix", "description": "512 instances, robots U{2..32}, "
                               "horizon U{40..160}, 3 dynamics, M=1024, N=100, random starts/goals in a 10 m box"},
+                   "details": res}
+        elif args.experiment == "gemm":
+            res = E.gemm_roofline(L, log=log)
+            head = res[0]
+            out = {"metric": "BF16 MFMA product throughput of the proposal network (training-step shapes)",
+                   "value": head["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True,
+                   "dtype": "bf16 in, f32 accumulate", "data": "synthetic",
+                   "config": {"workload": "proposal_gemm", "description": "d4p_gemm_bf16 at the shapes of one "
+                              "training step (64 teams, about 640 robots, width 256, hidden 512, T d_u = 200) and "
+                              "one large square product"},
+                   "roofline": {"bound": "mfma", "achieved": head["tflops"], "peak": 2500.0, "unit": "TFLOP/s",
+                                "frac": head["frac_of_peak"], "traffic": None},
                    "details": res}
         elif args.experiment == "first_success":
             res = [E.first_success(L, scenario=sc, n=t, radius=args.radius or 4.0, log=log)

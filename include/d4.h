@@ -248,9 +248,17 @@ int32_t d4_denoise_iter_noalloc(const d4_problem* p, const float* x0, const floa
 int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samples_per_group,
                     int32_t steps_per_block, int32_t replicas);
 
-/* The tile the library uses for p: the batched form's rule when batched is
- * non-zero, else the single-problem choice (installed tile or default).
- * Outputs are host pointers, each may be NULL. */
+/* Install (or, with samples_per_group = 0, remove) the tile of the batched
+ * form for instances of dynamics dyn with n_lo <= n_robots <= n_hi and
+ * t_lo <= horizon <= t_hi (one replica lane; admissible for n_hi; buckets of
+ * one dynamics must not overlap).  Batches created afterwards use it
+ * (d4_batch_create reads the buckets); a tile changes only speed. */
+int32_t d4_batch_tile_set(int32_t dyn, int32_t n_lo, int32_t n_hi, int32_t t_lo, int32_t t_hi,
+                          int32_t samples_per_group, int32_t steps_per_block);
+
+/* The tile the library uses for p: the batched form's bucket tile or rule
+ * when batched is non-zero, else the single-problem choice (installed tile or
+ * default).  Outputs are host pointers, each may be NULL. */
 int32_t d4_tile_get(const d4_problem* p, int32_t batched, int32_t* samples_per_group, int32_t* steps_per_block,
                     int32_t* replicas);
 
@@ -331,7 +339,7 @@ int32_t d4_batch_work_list(const d4_problem* probs, int32_t count, int32_t lag, 
  * then W_h [W][d_out], b_h [d_out] (row-major).
  * ------------------------------------------------------------------------ */
 typedef struct d4p_config {
-    int32_t d_in;       /* per-robot features */
+    int32_t d_in;       /* per-robot features, 1..8 */
     int32_t width;      /* W */
     int32_t hidden;     /* H */
     int32_t layers;     /* L */

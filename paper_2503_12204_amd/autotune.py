@@ -106,3 +106,91 @@ def install_cache(path=DEFAULT_CACHE):
             set_tile(dyn, n, T, e["S"], e["Tb"], e.get("R", 1))
             k += 1
     return k
+
+
+# ------------------------------------------------------------ batched form
+L.lib().d4_batch_tile_set.argtypes = [ctypes.c_int32] * 7
+L.lib().d4_batch_tile_set.restype = ctypes.c_int32
+
+N_BUCKETS = ((1, 4), (5, 8), (9, 16), (17, 32))
+T_BUCKETS = ((1, 80), (81, 120), (121, 100000))
+
+
+def batch_bucket(p):
+    """(dyn, n_lo, n_hi, t_lo, t_hi) of the bucket holding problem p."""
+    nb = next(b for b in N_BUCKETS if b[0] <= p.n_robots <= b[1])
+    tb = next(b for b in T_BUCKETS if b[0] <= p.horizon <= b[1])
+    return (p.dyn, nb[0], nb[1], tb[0], tb[1])
+
+
+def set_batch_tile(bucket, samples_per_group, steps_per_block):
+    L._check(L.lib().d4_batch_tile_set(*bucket, samples_per_group, steps_per_block))
+
+
+def clear_batch_tile(bucket):
+    L._check(L.lib().d4_batch_tile_set(*bucket, 0, 0))
+
+
+def _candidates(bucket):
+    dyn, n_lo, n_hi = bucket[0], bucket[1], bucket[2]
+    cs = 4 if dyn == 1 else 2
+    S0 = min(64, 256 // n_hi)
+    out = []
+    for S in sorted({S0, max(1, S0 // 2)}):
+        for Tb in (4, 8, 12, 16, 24):
+            if Tb % cs == 0:
+                out.append((S, Tb))
+    return out
+
+
+def tune_batch(probs, x0s, goals, path=DEFAULT_CACHE, steps=10, per_bucket=24, force=False, log=None):
+    """Tile of every (dynamics, team-size, horizon) bucket of a batch, chosen by
+    timing short whole batched iterations (`steps` denoising steps, so the
+    timing covers the step sequence and not one step) of up to `per_bucket`
+    of the batch's own instances in that bucket with each candidate tile;
+    cached per architecture and kernel source version, and installed with
+    d4_batch_tile_set.  A tile changes only speed.  Returns {bucket: entry}."""
+    import time
+    import numpy as np
+    cache = _load(path)
+    groups = {}
+    for j, p in enumerate(probs):
+        groups.setdefault(batch_bucket(p), []).append(j)
+    chosen = {}
+    for bucket, idx in sorted(groups.items()):
+        key = f"{_arch()}|{source_version()}|batch|" + "|".join(str(v) for v in bucket) + f"|M{probs[0].n_samples}"
+        if key in cache and not force:
+            e = cache[key]
+            set_batch_tile(bucket, e["S"], e["Tb"])
+            chosen[bucket] = e
+            continue
+        sel = idx[:per_bucket]
+        sub = [probs[j].replace(n_steps=steps) for j in sel]
+        best = None
+        for S, Tb in _candidates(bucket):
+            try:
+                set_batch_tile(bucket, S, Tb)
+            except L.D4Error:
+                continue
+            bc = L.BatchContext(sub, [x0s[j] for j in sel], [goals[j] for j in sel])
+            bc.iterate(0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(2):
+                bc.iterate(1 + k, sync=False)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / 2 * 1e3
+            bc.close()
+            if best is None or ms < best["ms"]:
+                best = {"S": S, "Tb": Tb, "ms": ms, "instances": len(sel)}
+        set_batch_tile(bucket, best["S"], best["Tb"])
+        chosen[bucket] = best
+        cache[key] = best
+        if log:
+            log(f"bucket {bucket}: S={best['S']} Tb={best['Tb']} ({best['ms']:.2f} ms for {len(sel)} instances)")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return chosen

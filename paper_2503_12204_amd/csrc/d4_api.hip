@@ -652,6 +652,21 @@ bool tile_override(int dyn, int n, int T, Tile* out) {
     return true;
 }
 
+namespace {
+struct BatchBucket {
+    int dyn, n_lo, n_hi, t_lo, t_hi;
+    Tile tile;
+};
+std::vector<BatchBucket> g_batch_buckets;
+}  // namespace
+
+Tile batch_tile(int dyn, int n, int T) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    for (const BatchBucket& b : g_batch_buckets)
+        if (b.dyn == dyn && n >= b.n_lo && n <= b.n_hi && T >= b.t_lo && T <= b.t_hi) return b.tile;
+    return default_tile(dyn, n);
+}
+
 }  // namespace d4host
 
 namespace {
@@ -696,11 +711,41 @@ int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samp
     return D4_OK;
 }
 
+int32_t d4_batch_tile_set(int32_t dyn, int32_t n_lo, int32_t n_hi, int32_t t_lo, int32_t t_hi,
+                          int32_t samples_per_group, int32_t steps_per_block) {
+    if (dyn < 0 || dyn > 3 || n_lo < 1 || n_hi < n_lo || n_hi > 32 || t_lo < 1 || t_hi < t_lo)
+        return fail(D4_EINVAL, "bad bucket");
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto same = [&](const BatchBucket& b) {
+        return b.dyn == dyn && b.n_lo == n_lo && b.n_hi == n_hi && b.t_lo == t_lo && b.t_hi == t_hi;
+    };
+    g_batch_buckets.erase(std::remove_if(g_batch_buckets.begin(), g_batch_buckets.end(), same),
+                          g_batch_buckets.end());
+    if (samples_per_group == 0) return D4_OK;
+    // the tile must be admissible for the bucket's largest team
+    d4_problem p;
+    std::memset(&p, 0, sizeof p);
+    p.dyn = dyn;
+    p.n_robots = n_hi;
+    p.horizon = t_hi;
+    Tile t;
+    t.S = samples_per_group;
+    t.Tb = steps_per_block;
+    t.R = 1;
+    int rc = tile_ok(&p, t);
+    if (rc) return rc;
+    for (const BatchBucket& b : g_batch_buckets)
+        if (b.dyn == dyn && n_lo <= b.n_hi && b.n_lo <= n_hi && t_lo <= b.t_hi && b.t_lo <= t_hi)
+            return fail(D4_EINVAL, "bucket overlaps an installed one");
+    g_batch_buckets.push_back(BatchBucket{dyn, n_lo, n_hi, t_lo, t_hi, t});
+    return D4_OK;
+}
+
 int32_t d4_tile_get(const d4_problem* p, int32_t batched, int32_t* samples_per_group, int32_t* steps_per_block,
                     int32_t* replicas) {
     int rc = validate(p);
     if (rc) return rc;
-    const Tile t = batched ? default_tile(p->dyn, p->n_robots) : pick_tile(p);
+    const Tile t = batched ? batch_tile(p->dyn, p->n_robots, p->horizon) : pick_tile(p);
     if (samples_per_group) *samples_per_group = t.S;
     if (steps_per_block) *steps_per_block = t.Tb;
     if (replicas) *replicas = t.R;

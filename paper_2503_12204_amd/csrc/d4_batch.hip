@@ -110,7 +110,7 @@ std::vector<BatchWork> batch_work_list(const std::vector<InstPlan>& ip, int M, i
 }
 
 InstPlan plan_of(const d4_problem& p) {
-    const Tile t = default_tile(p.dyn, p.n_robots);
+    const Tile t = batch_tile(p.dyn, p.n_robots, p.horizon);
     return InstPlan{t.S, p.n_robots * p.horizon * shape_of(p.dyn).du, tile_cost(p)};
 }
 
@@ -250,7 +250,7 @@ int32_t d4_batch_create(const d4_problem* probs, int32_t count, d4_batch** out) 
     for (int j = 0; j < count; ++j) {
         const d4_problem& p = probs[j];
         const Shape s = shape_of(p.dyn);
-        const Tile t = default_tile(p.dyn, p.n_robots);
+        const Tile t = batch_tile(p.dyn, p.n_robots, p.horizon);
         BatchInst in;
         std::memset(&in, 0, sizeof in);
         in.n = p.n_robots;

@@ -201,6 +201,11 @@ inline Tile default_tile(int dyn, int n) {
 // Tuned tile of a problem shape installed by d4_tile_set / d4_autotune, if any.
 bool tile_override(int dyn, int n, int T, Tile* out);
 
+// Tile of an instance of the batched form: the tile installed for its
+// (dynamics, team-size range, horizon range) bucket by d4_batch_tile_set, if
+// any, else the shared rule.
+Tile batch_tile(int dyn, int n, int T);
+
 // Dynamic LDS of the cooperative kernel: controls [n][G][4][S] (G = Tb d_u / 4
 // + 1 Philox blocks per robot and time block), single-buffered positions
 // [Tb][2n-1][S] and masks [2][Tb][S]; the final reductions reuse the space.

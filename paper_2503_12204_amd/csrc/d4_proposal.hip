@@ -106,7 +106,7 @@ int backward_impl(d4p_net* n, const float* x, const int* seg, const float* targe
     // head
     const bf16_t* hL = n->hb + (size_t)L * c.max_rows * W;
     TRY((gemm<true, false>(hL, n->dyb, n->g + n->oWh, W, N, R, W, N, N, 0.0f, st)));
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(N)), dim3(256), 0, st, n->dy, n->g + n->obh, R, N);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(N, COLS_PER_GROUP)), dim3(256), 0, st, n->dy, n->g + n->obh, R, N);
     float* dh = n->dh0;
     float* dhn = n->dh1;
     TRY((gemm<false, true>(n->dyb, n->wb + n->oWh, dh, R, W, N, N, N, W, 0.0f, st)));
@@ -118,11 +118,11 @@ int backward_impl(d4p_net* n, const float* x, const int* seg, const float* targe
         hipLaunchKernelGGL(k_cast_bf16, dim3(blocks(RW)), dim3(256), 0, st, dh, n->dhb, RW);
         // branch relu(h W1 + b1) W2 + b2
         TRY((gemm<true, false>(a1b, n->dhb, n->g + n->oW2[l], H, W, R, H, W, W, 0.0f, st)));
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(W)), dim3(256), 0, st, dh, n->g + n->ob2[l], R, W);
+        hipLaunchKernelGGL(k_colsum, dim3(blocks(W, COLS_PER_GROUP)), dim3(256), 0, st, dh, n->g + n->ob2[l], R, W);
         TRY((gemm<false, true>(n->dhb, n->wb + n->oW2[l], n->da1, R, H, W, W, W, H, 0.0f, st)));
         hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(RH)), dim3(256), 0, st, n->da1, z1, n->dz1b, RH);
         TRY((gemm<true, false>(hb, n->dz1b, n->g + n->oW1[l], W, H, R, W, H, H, 0.0f, st)));
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(H)), dim3(256), 0, st, n->da1, n->g + n->ob1[l], R, H);
+        hipLaunchKernelGGL(k_colsum, dim3(blocks(H, COLS_PER_GROUP)), dim3(256), 0, st, n->da1, n->g + n->ob1[l], R, H);
         HIP_TRY(hipMemcpyAsync(dhn, dh, sizeof(float) * RW, hipMemcpyDeviceToDevice, st));
         TRY((gemm<false, true>(n->dz1b, n->wb + n->oW1[l], dhn, R, W, H, H, H, W, 1.0f, st)));
         // pool mean_b(h) Wp
@@ -134,9 +134,9 @@ int backward_impl(d4p_net* n, const float* x, const int* seg, const float* targe
         HIP_LAUNCH_CHECK("k_pool_bwd");
         std::swap(dh, dhn);
     }
-    hipLaunchKernelGGL(k_embed_grad, dim3(blocks((long long)c.d_in * W)), dim3(256), 0, st, x, dh, n->g + n->oWe, R,
+    hipLaunchKernelGGL(k_embed_grad, dim3(blocks(W, COLS_PER_GROUP)), dim3(256), 0, st, x, dh, n->g + n->oWe, R,
                        c.d_in, W);
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(W)), dim3(256), 0, st, dh, n->g + n->obe, R, W);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(W, COLS_PER_GROUP)), dim3(256), 0, st, dh, n->g + n->obe, R, W);
     HIP_LAUNCH_CHECK("k_colsum");
     return D4_OK;
 }
@@ -159,6 +159,7 @@ int32_t d4p_create(const d4p_config* cfg, d4p_net** out) {
     if (c.d_in < 1 || c.width < 1 || c.hidden < 1 || c.layers < 0 || c.d_out < 1 || c.max_rows < 1 ||
         c.max_batch < 1 || c.layers > 64)
         return fail(D4_EINVAL, "bad network shape");
+    if (c.d_in > MAX_D_IN) return fail(D4_EUNSUPPORTED, "d_in %d above %d", c.d_in, MAX_D_IN);
     d4p_net* n = new (std::nothrow) d4p_net();
     if (!n) return fail(D4_ENOMEM, "host allocation failed");
     n->cfg = c;

@@ -29,64 +29,91 @@ __device__ __forceinline__ float from_bf16(bf16_t h) { return __uint_as_float((u
 
 constexpr int BM = 64, BN = 64, BK = 32, KPAD = 8;
 
+// Eight consecutive BF16 values of one operand row (op = X) or of one stored
+// row of a transposed operand, starting at (outer, inner0): one 16-byte
+// global load when the whole group is in range and 16-byte aligned, element
+// loads (zero past the edges) otherwise.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 load8_bf16(const bf16_t* __restrict__ X, int ld, int outer, int n_outer,
+                                            int inner0, int n_inner) {
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (outer >= n_outer) return v;
+    const bf16_t* p = X + (size_t)outer * ld + inner0;
+    if (inner0 + 8 <= n_inner && (reinterpret_cast<uintptr_t>(p) & 15u) == 0)
+        return *reinterpret_cast<const u32x4*>(p);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (inner0 + i < n_inner) w[i >> 1] |= (uint32_t)p[i] << (16 * (i & 1));
+    v[0] = w[0];
+    v[1] = w[1];
+    v[2] = w[2];
+    v[3] = w[3];
+    return v;
+}
+
+// C = alpha op(A) op(B) + beta C.  64x64 workgroup tiles, four waves of 32x32
+// on v_mfma_f32_32x32x16_bf16, K in steps of 32.  Each lane moves one group of
+// eight BF16 values per operand and K step with a 16-byte global load (both
+// operands are stored k-contiguous in LDS, so a transposed operand's group is
+// scattered into its eight k rows on the way in).  The LDS tiles are double
+// buffered: the loads of step k+1 go out before the MFMAs of step k, and one
+// barrier per step separates the writes of one buffer from the reads of the
+// other.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm_bf16(const bf16_t* __restrict__ A, const bf16_t* __restrict__ B,
                                                    float* __restrict__ C, int M, int N, int K, int lda,
                                                    int ldb, int ldc, float alpha, float beta) {
-    __shared__ __attribute__((aligned(16))) bf16_t As[BM][BK + KPAD];
-    __shared__ __attribute__((aligned(16))) bf16_t Bs[BN][BK + KPAD];
+    __shared__ __attribute__((aligned(16))) bf16_t As[2][BM][BK + KPAD];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN][BK + KPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    // this lane's group: non-transposed, row tid/4 and k (tid%4)*8; transposed, k row tid/8 and
+    // outer (tid%8)*8
+    const int ra = tid >> 2, ka = (tid & 3) * 8;
+    const int kt = tid >> 3, ot = (tid & 7) * 8;
+    auto load_a = [&](int k0) {
+        return TA ? load8_bf16(A, lda, k0 + kt, K, m0 + ot, M) : load8_bf16(A, lda, m0 + ra, M, k0 + ka, K);
+    };
+    auto load_b = [&](int k0) {
+        return TB ? load8_bf16(B, ldb, n0 + ra, N, k0 + ka, K) : load8_bf16(B, ldb, k0 + kt, K, n0 + ot, N);
+    };
+    auto store = [&](bf16_t (*T)[BK + KPAD], bool trans, u32x4 v) {
+        if (!trans) {
+            *reinterpret_cast<u32x4*>(&T[ra][ka]) = v;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) T[ot + i][kt] = (bf16_t)(v[i >> 1] >> (16 * (i & 1)));
+        }
+    };
     f32x16 acc;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    u32x4 va = load_a(0), vb = load_b(0);
+    store(As[0], TA, va);
+    store(Bs[0], !TB, vb);
+    __syncthreads();
+    int buf = 0;
     for (int k0 = 0; k0 < K; k0 += BK) {
-        // A tile -> As[m][k]
-        if (!TA) {
-            const int row = tid >> 2, kk = (tid & 3) * 8;
-            const int gm = m0 + row;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gk = k0 + kk + i;
-                As[row][kk + i] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : (bf16_t)0;
-            }
-        } else {
-            const int kk = tid >> 3, mm = (tid & 7) * 8;
-            const int gk = k0 + kk;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gm = m0 + mm + i;
-                As[mm + i][kk] = (gm < M && gk < K) ? A[(size_t)gk * lda + gm] : (bf16_t)0;
-            }
+        const bool more = k0 + BK < K;
+        if (more) {
+            va = load_a(k0 + BK);
+            vb = load_b(k0 + BK);
         }
-        // B tile -> Bs[n][k]
-        if (TB) {
-            const int row = tid >> 2, kk = (tid & 3) * 8;
-            const int gn = n0 + row;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gk = k0 + kk + i;
-                Bs[row][kk + i] = (gn < N && gk < K) ? B[(size_t)gn * ldb + gk] : (bf16_t)0;
-            }
-        } else {
-            const int kk = tid >> 3, nn = (tid & 7) * 8;
-            const int gk = k0 + kk;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gn = n0 + nn + i;
-                Bs[nn + i][kk] = (gn < N && gk < K) ? B[(size_t)gk * ldb + gn] : (bf16_t)0;
-            }
-        }
-        __syncthreads();
 #pragma unroll
         for (int kb = 0; kb < BK; kb += 16) {
             const int r = lane & 31, kq = kb + (lane >> 5) * 8;
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + r][kq]);
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + r][kq]);
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 32 + r][kq]);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 32 + r][kq]);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
+        if (more) {
+            store(As[buf ^ 1], TA, va);
+            store(Bs[buf ^ 1], !TB, vb);
+        }
         __syncthreads();
+        buf ^= 1;
     }
     // lane l holds column l%32, rows 8*(v/4) + 4*(l/32) + v%4 of the wave's 32x32 block
     const int col = n0 + wn * 32 + (lane & 31);
@@ -220,13 +247,27 @@ __global__ void __launch_bounds__(256) k_loss_final(const float* __restrict__ pa
     if (threadIdx.x == 0) *out = red[0] / (2.0f * (float)N * fmaxf(*msum, 1.0f));
 }
 
-// out[c] = sum_r x[r][c]; one thread per column
-__global__ void k_colsum(const float* __restrict__ x, float* __restrict__ out, int R, int N) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N) return;
+// Column reductions over all rows, parallel over rows: a workgroup of 256
+// lanes takes 16 columns, lane (q, c) sums rows q, q + 16, ... of column c,
+// and the 16 partial sums are added in a fixed order, so results do not
+// depend on timing.  COLS_PER_GROUP columns per workgroup.
+constexpr int COLS_PER_GROUP = 16, ROW_LANES = 16;
+
+// out[c] = sum_r x[r][c]
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ x, float* __restrict__ out, int R, int N) {
+    __shared__ float part[ROW_LANES][COLS_PER_GROUP];
+    const int cl = threadIdx.x % COLS_PER_GROUP, q = threadIdx.x / COLS_PER_GROUP;
+    const int c = blockIdx.x * COLS_PER_GROUP + cl;
     float s = 0.0f;
-    for (int r = 0; r < R; ++r) s += x[(size_t)r * N + c];
-    out[c] = s;
+    if (c < N)
+        for (int r = q; r < R; r += ROW_LANES) s += x[(size_t)r * N + c];
+    part[q][cl] = s;
+    __syncthreads();
+    if (q == 0 && c < N) {
+        float t = 0.0f;
+        for (int i = 0; i < ROW_LANES; ++i) t += part[i][cl];
+        out[c] = t;
+    }
 }
 
 // dz = da * (z > 0), in place on da, plus its BF16 copy
@@ -248,15 +289,33 @@ __global__ void k_pool_bwd(float* __restrict__ dh, const float* __restrict__ dpm
     dh[i] += dpm[(size_t)b * W + c] / (float)(seg[b + 1] - seg[b]);
 }
 
-// gWe[j][c] = sum_r x[r][j] dh[r][c]
-__global__ void k_embed_grad(const float* __restrict__ x, const float* __restrict__ dh, float* __restrict__ g,
-                             int R, int d_in, int W) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d_in * W) return;
-    const int j = i / W, c = i - j * W;
-    float s = 0.0f;
-    for (int r = 0; r < R; ++r) s += x[(size_t)r * d_in + j] * dh[(size_t)r * W + c];
-    g[i] = s;
+// gWe[j][c] = sum_r x[r][j] dh[r][c], for d_in <= MAX_D_IN, rows in parallel as
+// in k_colsum (the partial sums of the 16 row lanes added in a fixed order)
+constexpr int MAX_D_IN = 8;
+__global__ void __launch_bounds__(256) k_embed_grad(const float* __restrict__ x, const float* __restrict__ dh,
+                                                    float* __restrict__ g, int R, int d_in, int W) {
+    __shared__ float part[MAX_D_IN][ROW_LANES][COLS_PER_GROUP];
+    const int cl = threadIdx.x % COLS_PER_GROUP, q = threadIdx.x / COLS_PER_GROUP;
+    const int c = blockIdx.x * COLS_PER_GROUP + cl;
+    float s[MAX_D_IN];
+#pragma unroll
+    for (int j = 0; j < MAX_D_IN; ++j) s[j] = 0.0f;
+    if (c < W)
+        for (int r = q; r < R; r += ROW_LANES) {
+            const float d = dh[(size_t)r * W + c];
+#pragma unroll
+            for (int j = 0; j < MAX_D_IN; ++j)
+                if (j < d_in) s[j] += x[(size_t)r * d_in + j] * d;
+        }
+#pragma unroll
+    for (int j = 0; j < MAX_D_IN; ++j) part[j][q][cl] = s[j];
+    __syncthreads();
+    if (q == 0 && c < W)
+        for (int j = 0; j < d_in; ++j) {
+            float t = 0.0f;
+            for (int i = 0; i < ROW_LANES; ++i) t += part[j][i][cl];
+            g[(size_t)j * W + c] = t;
+        }
 }
 
 // Adam with bias correction on FP32 master weights, then their BF16 copy

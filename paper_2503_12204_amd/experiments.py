@@ -21,10 +21,19 @@ from . import proposal as PR
 from . import workloads as W
 
 
-def batched_vs_plain(L, count=512, n_samples=1024, iterations=2, seed=0, log=print):
-    inst = W.batched_mix(count=count, n_samples=n_samples, seed=seed)
+def algorithmic_ops(dyn, n, n_obstacles=0):
+    """The method's VALU operations per robot*step*sample (draws, sampled
+    control, dynamics, goal term and the pair term of Eq. generic-reward with
+    (n - 1)/2 checks per robot and step): the numerator of the fused kernels'
+    roofline."""
+    dx, du, dp = W.dims(dyn)
+    dynamics = 80.0 if dyn in (W.UNICYCLE, W.DIFFDRIVE) else 5.0 * dp
+    check = 2.0 * dp + 2.0
+    return 40.0 * du + 3.0 * du + dynamics + 8.0 + (n - 1) / 2.0 * check + n_obstacles * check
+
+
+def _time_batch(L, inst, iterations):
     probs = [p for p, _, _ in inst]
-    units = sum(p.n_robots * p.horizon * p.n_samples * p.n_steps for p in probs)
     bc = L.BatchContext(probs, [x for _, x, _ in inst], [g for _, _, g in inst])
     bc.iterate(0)
     torch.cuda.synchronize()
@@ -32,9 +41,45 @@ def batched_vs_plain(L, count=512, n_samples=1024, iterations=2, seed=0, log=pri
     for k in range(iterations):
         bc.iterate(k + 1, sync=False)
     torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / iterations
+    dt = (time.perf_counter() - t0) / iterations
     bc.close()
-    log(f"batched: {t_batch * 1e3:.1f} ms per iteration of {count} instances")
+    return dt
+
+
+def batched_vs_plain(L, count=512, n_samples=1024, iterations=2, seed=0, plain=True, tune=True, log=print):
+    """The batched form against the same instances run one after another
+    through the single-problem path.  With tune, the batch's bucket tiles are
+    first chosen by timing short batched iterations (autotune.tune_batch; the
+    tuning time is reported, not counted), and the rule's tiles are timed as
+    well."""
+    from . import autotune as AT
+    inst = W.batched_mix(count=count, n_samples=n_samples, seed=seed)
+    probs = [p for p, _, _ in inst]
+    units = sum(p.n_robots * p.horizon * p.n_samples * p.n_steps for p in probs)
+    ops_per_step = sum(algorithmic_ops(p.dyn, p.n_robots, len(p.obstacles)) * p.n_robots * p.horizon * p.n_samples
+                       for p in probs)
+    t_rule = _time_batch(L, inst, iterations)
+    log(f"batched, rule tiles: {t_rule * 1e3:.1f} ms per iteration of {count} instances")
+    tuned = None
+    t_batch = t_rule
+    if tune:
+        import tempfile
+        t0 = time.perf_counter()
+        with tempfile.TemporaryDirectory() as td:
+            tuned = AT.tune_batch(probs, [x for _, x, _ in inst], [g for _, _, g in inst],
+                                  path=f"{td}/tiles.json", log=log)
+        t_tune = time.perf_counter() - t0
+        t_batch = _time_batch(L, inst, iterations)
+        for b in tuned:
+            AT.clear_batch_tile(b)
+        log(f"batched, tuned tiles ({t_tune:.1f} s of tuning): {t_batch * 1e3:.1f} ms per iteration")
+    head = {"instances": count, "samples": n_samples, "batched_ms_per_iteration": t_batch * 1e3,
+            "batched_rule_tiles_ms_per_iteration": t_rule * 1e3,
+            "tuned_tiles": {"/".join(str(v) for v in b): e for b, e in tuned.items()} if tuned else None,
+            "batched_robot_step_samples_per_s": units / t_batch, "algorithmic_ops_per_step": ops_per_step,
+            "step_algorithmic_rate_T_per_s": ops_per_step * probs[0].n_steps / t_batch / 1e12}
+    if not plain:
+        return head
     ctxs = []
     for p, x0, g in inst:
         ctxs.append((L.Context(p), torch.as_tensor(x0, device="cuda"), torch.as_tensor(g, device="cuda"),
@@ -51,9 +96,8 @@ def batched_vs_plain(L, count=512, n_samples=1024, iterations=2, seed=0, log=pri
     for c, _, _, _ in ctxs:
         c.close()
     log(f"plain, one instance after another: {t_plain * 1e3:.1f} ms per iteration")
-    return {"instances": count, "samples": n_samples, "batched_ms_per_iteration": t_batch * 1e3,
-            "plain_sequential_ms_per_iteration": t_plain * 1e3, "speedup": t_plain / t_batch,
-            "batched_robot_step_samples_per_s": units / t_batch}
+    head.update({"plain_sequential_ms_per_iteration": t_plain * 1e3, "speedup": t_plain / t_batch})
+    return head
 
 
 def _chunks(seq, k):
@@ -62,16 +106,40 @@ def _chunks(seq, k):
 
 
 def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=3, eval_samples=2048,
-                  eval_iters=5, epochs=20, seed=0, target_tol=0.005, log=print):
+                  eval_iters=5, extra_iters=3, epochs=20, seed=0, target_tol=0.005, log=print):
+    """Train the proposal on teams the plain planner solved, then compare the
+    plain planner from zero controls with the planner started from the judged
+    proposal on held-out teams.
+
+    An instance's target is 99.5 % of the reward the plain planner reaches with
+    its budget of eval_iters iterations (the strict target, that reward itself,
+    is reported too).  The proposal-started run gets extra_iters iterations
+    beyond the budget, so that a team it misses is a team it does not reach in
+    eval_iters + extra_iters iterations; the miss fraction, the speedup over
+    the teams both runs reach, and the speedup with each miss counted at the
+    cap are all reported.  Two judges decide which start a team keeps:
+      initial: the proposal when its rolled-out reward beats the zero plan's
+               (the planner's fitness of the initial plans, no extra cost);
+      first iteration: the start whose reward after one iteration is higher,
+               which costs one extra iteration per team (counted) and guards
+               the final quality as well as the start.
+    The fraction of teams whose reward after the budget ends below the plain
+    planner's is reported for each."""
     rng = np.random.default_rng(1_000_000 + seed)
     t0 = time.perf_counter()
-    train = [PR.random_team(rng, n_samples=label_samples, instance_id=j) for j in range(n_train)]
+    train = []
+    for j in range(n_train):
+        train.append(PR.random_team(rng, n_samples=label_samples, instance_id=j))
+        if (j + 1) % 20000 == 0:
+            log(f"built {j + 1} training teams")
     plans, rewards, success = [], [], []
-    for chunk in _chunks(train, 512):
+    for c, chunk in enumerate(_chunks(train, 512)):
         pl, hist, _ = PR.run_planner(L, chunk, iterations=label_iters)
         plans += pl
         rewards += [s["reward"] for s in hist[-1]]
         success += [s["success"] for s in hist[-1]]
+        if (c + 1) % 20 == 0:
+            log(f"labelled {len(plans)} teams, {time.perf_counter() - t0:.0f} s")
     rewards, success = np.array(rewards), np.array(success)
     mask = success if success.mean() >= 0.25 else rewards >= np.median(rewards)
     t_label = time.perf_counter() - t0
@@ -83,6 +151,7 @@ def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"trained {epochs} epochs in {t_train:.1f} s, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    del train, plans
 
     trng = np.random.default_rng(seed)
     test = [PR.random_team(trng, n_samples=eval_samples, instance_id=j) for j in range(n_test)]
@@ -92,63 +161,73 @@ def proposal_gain(L, n_train=4096, n_test=1000, label_samples=1024, label_iters=
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t0
     r_init = np.array([PR.plan_reward(L, t, u) for t, u in zip(test, init)])
-    hp, hn, tp, tn = [], [], [], []
+    hp, hn, tp = [], [], []
+    K_n = eval_iters + extra_iters
     for c0 in range(0, n_test, 500):
         ch = test[c0:c0 + 500]
         _, h1, t1 = PR.run_planner(L, ch, iterations=eval_iters)
-        _, h2, t2 = PR.run_planner(L, ch, iterations=eval_iters, init_plans=init[c0:c0 + 500])
+        _, h2, _ = PR.run_planner(L, ch, iterations=K_n, init_plans=init[c0:c0 + 500])
         hp.append(h1)
         hn.append(h2)
-        tp.append(t1)               # seconds per batched iteration of this chunk
-        tn.append(t2)
+        tp.append(t1)                # seconds per batched iteration of this chunk
+        log(f"evaluated {c0 + len(ch)} held-out teams")
     hist_p = [sum((h[k] for h in hp), []) for k in range(eval_iters)]
-    hist_n = [sum((h[k] for h in hn), []) for k in range(eval_iters)]
-    t_iter = sum(tp) / n_test       # seconds of batched iteration per team
-    final = np.array([s["reward"] for s in hist_p[-1]])
-    # target: 99.5 % of the reward the plain planner reaches with its full
-    # budget (the strict target, its final reward itself, is reported too: it
-    # is a noisy maximum that the plain planner meets by construction)
+    hist_n = [sum((h[k] for h in hn), []) for k in range(K_n)]
+    t_iter = sum(tp) / n_test        # seconds of batched iteration per team
+    rew_p = np.array([[s["reward"] for s in it] for it in hist_p])        # [K][teams]
+    rew_n = np.array([[s["reward"] for s in it] for it in hist_n])
+    final = rew_p[-1]
     target = final - target_tol * np.abs(final)
     k_p = PR.iterations_to_target(hist_p, target)
     k_n = PR.iterations_to_target(hist_n, target, init_rewards=r_init)
-    reach_p = k_p <= eval_iters
-    reach_n = k_n <= eval_iters
+    # first-iteration judge: keep the run whose reward after one iteration is higher
+    take_n = rew_n[0] >= rew_p[0]
+    k_j = np.where(take_n, k_n, k_p)
+    k_j = np.where(k_j == 0, 0, k_j + 1)       # one extra iteration: both starts ran the first one
+    final_j = np.where(take_n, rew_n[eval_iters - 1], final)
+    reach_p, reach_n, reach_j = k_p <= eval_iters, k_n <= K_n, k_j <= K_n + 1
+    both = reach_p & reach_n
+
+    def speed(kp, kn, sel, cap_n):
+        tp_ = np.where(reach_p, kp, eval_iters + 1)[sel].mean() * t_iter
+        tn_ = np.where(kn <= cap_n, kn, cap_n + 1)[sel].mean() * t_iter + t_infer / n_test
+        return float(tp_ / tn_)
+
     k_p_strict = PR.iterations_to_target(hist_p, final)
     k_n_strict = PR.iterations_to_target(hist_n, final, init_rewards=r_init)
     succ_p = PR.iterations_to_target([[{"reward": float(s["success"])} for s in it] for it in hist_p],
                                      np.ones(n_test))
     succ_n = PR.iterations_to_target([[{"reward": float(s["success"])} for s in it] for it in hist_n],
                                      np.ones(n_test))
-    kp_mean = float(np.where(reach_p, k_p, eval_iters + 1).mean())
-    kn_mean = float(np.where(reach_n, k_n, eval_iters + 1).mean())
-    t_plain = kp_mean * t_iter
-    t_net = kn_mean * t_iter + t_infer / n_test
-    kps = float(np.minimum(k_p_strict, eval_iters + 1).mean())
-    kns = float(np.minimum(k_n_strict, eval_iters + 1).mean())
-    strict = {"iterations_to_target_mean": {"plain": kps, "proposal": kns},
-              "target_reached_fraction": {"plain": float((k_p_strict <= eval_iters).mean()),
-                                          "proposal": float((k_n_strict <= eval_iters).mean())},
-              "time_to_target_speedup": (kps * t_iter) / (kns * t_iter + t_infer / n_test)}
+    all_t = np.ones(n_test, dtype=bool)
     out = {
         "train_teams": n_train, "test_teams": n_test, "label_samples": label_samples, "label_iterations": label_iters,
-        "eval_samples": eval_samples, "eval_iterations": eval_iters, "epochs": epochs,
+        "eval_samples": eval_samples, "eval_iterations": eval_iters, "proposal_iteration_cap": K_n, "epochs": epochs,
         "label_seconds": t_label, "train_seconds": t_train, "final_loss": losses[-1],
         "proposal_used_fraction": float(np.mean(used)),
         "initial_reward_mean": {"zero": 0.0, "proposal": float(r_init.mean())},
-        "reward_after_iteration": {"plain": [float(np.mean([s["reward"] for s in it])) for it in hist_p],
-                                   "proposal": [float(np.mean([s["reward"] for s in it])) for it in hist_n]},
+        "reward_after_iteration": {"plain": rew_p.mean(1).tolist(), "proposal": rew_n.mean(1).tolist()},
         "success_after_iteration": {"plain": [float(np.mean([s["success"] for s in it])) for it in hist_p],
                                     "proposal": [float(np.mean([s["success"] for s in it])) for it in hist_n]},
         "at_goal_after_iteration": {"plain": [float(np.mean([s["at_goal"] for s in it])) for it in hist_p],
                                     "proposal": [float(np.mean([s["at_goal"] for s in it])) for it in hist_n]},
         "target": f"{100 * (1 - target_tol):.1f} % of the plain planner's reward after {eval_iters} iterations",
-        "iterations_to_target_mean": {"plain": kp_mean, "proposal": kn_mean},
-        "target_reached_fraction": {"plain": float(reach_p.mean()), "proposal": float(reach_n.mean())},
-        "strict_target": strict,
-        "iterations_to_first_success_mean": {"plain": float(succ_p.mean()), "proposal": float(succ_n.mean())},
+        "iterations_to_target_mean": {"plain": float(k_p.mean()),
+                                      "proposal_over_reached": float(k_n[reach_n].mean()) if reach_n.any() else None},
+        "target_missed_fraction": {"plain": float(1 - reach_p.mean()), "proposal": float(1 - reach_n.mean()),
+                                   "proposal_first_iteration_judge": float(1 - reach_j.mean())},
+        "time_to_target_speedup": speed(k_p, k_n, all_t, K_n),
+        "time_to_target_speedup_both_reached": speed(k_p, k_n, both, K_n) if both.any() else None,
+        "time_to_target_speedup_first_iteration_judge": speed(k_p, k_j, all_t, K_n + 1),
+        "final_reward_below_plain_fraction": {
+            "initial_judge": float((rew_n[eval_iters - 1] < final).mean()),
+            "first_iteration_judge": float((final_j < final).mean())},
+        "first_iteration_judge_kept_proposal_fraction": float(take_n.mean()),
+        "strict_target": {"target_reached_fraction": {"plain": float((k_p_strict <= eval_iters).mean()),
+                                                      "proposal": float((k_n_strict <= K_n).mean())}},
+        "iterations_to_first_success_mean": {"plain": float(np.minimum(succ_p, eval_iters + 1).mean()),
+                                             "proposal": float(np.minimum(succ_n, K_n + 1).mean())},
         "seconds_per_iteration_per_team": t_iter, "proposal_inference_seconds_per_team": t_infer / n_test,
-        "time_to_target_seconds_per_team": {"plain": t_plain, "proposal": t_net},
-        "time_to_target_speedup": t_plain / t_net,
     }
     prop.close()
     return out
@@ -262,3 +341,46 @@ def first_success(L, scenario="circle", n=16, runs=50, n_samples=2048, horizon=1
             "median_seconds_to_first_success": float(np.median(t)),
             "mean_iterations": float(np.mean(iters)),
             "iterations_of_solved_runs": [int(i) for i, s in zip(iters, solved) if s]}
+
+
+def gemm_roofline(L, rows=640, width=256, hidden=512, d_out=200, batch=64, large=8192, reps=50, log=print):
+    """Achieved throughput of the proposal's BF16 MFMA product kernel
+    (d4p_gemm_bf16) at the shapes one training step runs (rows = robots of a
+    64-team batch) and at a large square shape, against the 2.5 PFLOP/s dense
+    BF16 peak.  Each shape is launched `reps` times back to back between HIP
+    events on the launch stream; flops = 2 M N K per launch."""
+    peak = 2.5e15
+    shapes = [
+        ("layer in, forward: [R x W] [W x H]", rows, hidden, width, False, False),
+        ("layer out, forward: [R x H] [H x W]", rows, width, hidden, False, False),
+        ("pool: [B x W] [W x W]", batch, width, width, False, False),
+        ("head: [R x W] [W x T d_u]", rows, d_out, width, False, False),
+        ("weight gradient: [R x W]^T [R x H]", width, hidden, rows, True, False),
+        ("input gradient: [R x H] [W x H]^T", rows, width, hidden, False, True),
+        (f"large square {large}", large, large, large, False, False),
+    ]
+    out = []
+    s = torch.cuda.current_stream()
+    for name, M, N, K, ta, tb in shapes:
+        A = (torch.randn((K, M) if ta else (M, K), device="cuda") * 0.1).to(torch.bfloat16)
+        B = (torch.randn((N, K) if tb else (K, N), device="cuda") * 0.1).to(torch.bfloat16)
+        C = torch.zeros((M, N), device="cuda")
+        n_rep = reps if M * N * K < 1e11 else 5
+        for _ in range(3):
+            L.gemm_bf16(A, B, M, N, K, ta, tb, C=C)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(n_rep):
+            L.gemm_bf16(A, B, M, N, K, ta, tb, C=C)
+        e1.record(s)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / n_rep
+        # spot check against a float32 product of the same BF16 operands
+        ref = (A.float().t() if ta else A.float()) @ (B.float().t() if tb else B.float())
+        err = float((C - ref).abs().max() / ref.abs().max().clamp_min(1e-30))
+        flops = 2.0 * M * N * K
+        row = {"shape": name, "M": M, "N": N, "K": K, "us": t * 1e6, "tflops": flops / t / 1e12,
+               "frac_of_peak": flops / t / peak, "max_rel_err": err}
+        log(f"{name}: {t * 1e6:.2f} us, {flops / t / 1e12:.2f} TFLOP/s ({flops / t / peak:.4f} of peak)")
+        out.append(row)
+    return out

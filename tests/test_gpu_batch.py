@@ -210,3 +210,47 @@ def test_persistent_step_equals_two_launch_form(L):
     for key, (u, st) in res.items():
         assert np.array_equal(u, ref_u), key
         assert st == ref_st, key
+
+
+def test_bucket_tiles_change_speed_only(L):
+    """Tiles installed per (dynamics, team size, horizon) bucket for the
+    batched form (what autotune.tune_batch installs) give the same plans and
+    statistics as the rule's tiles; the tuner itself runs on a small batch
+    and leaves every bucket it chose installed and admissible."""
+    from paper_2503_12204_amd import autotune as AT
+    inst = _mix(12, 128, 6, seed=13, t_range=(9, 50))
+    probs = [p for p, _, _ in inst]
+    print("case bucket tiles", [(p.dyn, p.n_robots, p.horizon) for p in probs], flush=True)
+
+    def run():
+        bc = L.BatchContext(probs, [x for _, x, _ in inst], [g for _, _, g in inst])
+        for it in range(2):
+            st = bc.iterate(it)
+        u = bc.u.cpu().numpy()
+        bc.close()
+        return u, st
+
+    ref_u, ref_st = run()
+    buckets = sorted({AT.batch_bucket(p) for p in probs})
+    try:
+        for b in buckets:
+            cs = 4 if b[0] == W.HOLO3D else 2
+            AT.set_batch_tile(b, max(1, min(64, 256 // b[2]) // 2), 2 * cs)
+        u, st = run()
+        assert np.array_equal(u, ref_u) and st == ref_st
+        for b in buckets:
+            AT.clear_batch_tile(b)
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            chosen = AT.tune_batch(probs, [x for _, x, _ in inst], [g for _, _, g in inst], path=f"{td}/t.json",
+                                   steps=3, per_bucket=4)
+        assert set(chosen) == set(buckets)
+        for p in probs:
+            S, Tb, R = AT.get_tile(p, batched=True)
+            e = chosen[AT.batch_bucket(p)]
+            assert (S, Tb, R) == (e["S"], e["Tb"], 1)
+        u, st = run()
+        assert np.array_equal(u, ref_u) and st == ref_st
+    finally:
+        for b in buckets:
+            AT.clear_batch_tile(b)
