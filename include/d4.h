@@ -250,8 +250,10 @@ int32_t d4_tile_set(int32_t dyn, int32_t n_robots, int32_t horizon, int32_t samp
 
 /* Install (or, with samples_per_group = 0, remove) the tile of the batched
  * form for instances of dynamics dyn with n_lo <= n_robots <= n_hi and
- * t_lo <= horizon <= t_hi (one replica lane; admissible for n_hi; buckets of
- * one dynamics must not overlap).  Batches created afterwards use it
+ * t_lo <= horizon <= t_hi (one replica lane; admissible for n_hi, and within
+ * the 56 KiB of LDS that keeps two reward workgroups per CU, else
+ * D4_EUNSUPPORTED: the largest request sets every workgroup's; buckets of one
+ * dynamics must not overlap).  Batches created afterwards use it
  * (d4_batch_create reads the buckets); a tile changes only speed. */
 int32_t d4_batch_tile_set(int32_t dyn, int32_t n_lo, int32_t n_hi, int32_t t_lo, int32_t t_hi,
                           int32_t samples_per_group, int32_t steps_per_block);

@@ -143,13 +143,17 @@ def _candidates(bucket):
     return out
 
 
-def tune_batch(probs, x0s, goals, path=DEFAULT_CACHE, steps=10, per_bucket=24, force=False, log=None):
+def tune_batch(probs, x0s, goals, path=DEFAULT_CACHE, steps=10, min_tiles=1024, force=False, log=None):
     """Tile of every (dynamics, team-size, horizon) bucket of a batch, chosen by
     timing short whole batched iterations (`steps` denoising steps, so the
-    timing covers the step sequence and not one step) of up to `per_bucket`
-    of the batch's own instances in that bucket with each candidate tile;
-    cached per architecture and kernel source version, and installed with
-    d4_batch_tile_set.  A tile changes only speed.  Returns {bucket: entry}."""
+    timing covers the step sequence and not one step) of a sub-batch of the
+    batch's own instances in that bucket, repeated under new instance ids
+    until one launch holds at least `min_tiles` reward tiles (so that the
+    sub-batch fills the GPU as the whole batch does), with each candidate
+    tile; cached per architecture and kernel source version, and installed
+    with d4_batch_tile_set, which refuses tiles whose LDS would lower the
+    whole batch's occupancy.  A tile changes only speed.  Returns
+    {bucket: entry}."""
     import time
     import numpy as np
     cache = _load(path)
@@ -164,8 +168,11 @@ def tune_batch(probs, x0s, goals, path=DEFAULT_CACHE, steps=10, per_bucket=24, f
             set_batch_tile(bucket, e["S"], e["Tb"])
             chosen[bucket] = e
             continue
-        sel = idx[:per_bucket]
-        sub = [probs[j].replace(n_steps=steps) for j in sel]
+        S_rule = min(64, 256 // bucket[2])
+        tiles_each = -(-probs[0].n_samples // S_rule)
+        reps = -(-min_tiles // (tiles_each * len(idx)))
+        sel = [idx[i % len(idx)] for i in range(len(idx) * max(1, reps))]
+        sub = [probs[j].replace(n_steps=steps, instance_id=r) for r, j in enumerate(sel)]
         best = None
         for S, Tb in _candidates(bucket):
             try:

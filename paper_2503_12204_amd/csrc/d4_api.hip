@@ -734,6 +734,9 @@ int32_t d4_batch_tile_set(int32_t dyn, int32_t n_lo, int32_t n_hi, int32_t t_lo,
     t.R = 1;
     int rc = tile_ok(&p, t);
     if (rc) return rc;
+    if (rollfit_lds(&p, t) > LDS_TWO_PER_CU)
+        return fail(D4_EUNSUPPORTED, "bucket tile needs %zu bytes of LDS, above the %zu of two workgroups per CU",
+                    rollfit_lds(&p, t), LDS_TWO_PER_CU);
     for (const BatchBucket& b : g_batch_buckets)
         if (b.dyn == dyn && n_lo <= b.n_hi && b.n_lo <= n_hi && t_lo <= b.t_hi && b.t_lo <= t_hi)
             return fail(D4_EINVAL, "bucket overlaps an installed one");

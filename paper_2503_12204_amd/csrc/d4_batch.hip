@@ -41,8 +41,6 @@ struct d4_batch {
 
 namespace {
 
-// dynamic LDS of a reward workgroup that leaves room for two, not three, on a CU
-constexpr size_t LDS_TWO_PER_CU = 56 * 1024;
 
 bool same_sampler(const d4_problem& a, const d4_problem& b) {
     return a.n_samples == b.n_samples && a.n_steps == b.n_steps && a.temperature == b.temperature &&

@@ -60,6 +60,12 @@ inline int fail(int code, const char* fmt, ...) {
 // the kernels' static arrays (staged obstacles, reductions).
 constexpr size_t LDS_DYNAMIC_MAX = 160 * 1024 - 1024;
 
+// Dynamic LDS every reward workgroup of the batched form requests: room for
+// two on a CU, not three (the batched kernel carries every model's code, and
+// three workgroups per CU ran a mixed batch 45 % slower).  A bucket tile
+// must fit under it, since the largest request sets every workgroup's.
+constexpr size_t LDS_TWO_PER_CU = 56 * 1024;
+
 struct Shape {
     int dx, du, dp;
 };

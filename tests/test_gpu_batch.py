@@ -243,7 +243,7 @@ def test_bucket_tiles_change_speed_only(L):
         import tempfile
         with tempfile.TemporaryDirectory() as td:
             chosen = AT.tune_batch(probs, [x for _, x, _ in inst], [g for _, _, g in inst], path=f"{td}/t.json",
-                                   steps=3, per_bucket=4)
+                                   steps=3, min_tiles=64)
         assert set(chosen) == set(buckets)
         for p in probs:
             S, Tb, R = AT.get_tile(p, batched=True)
