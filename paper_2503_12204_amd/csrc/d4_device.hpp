@@ -114,11 +114,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 // so that P dependent chains are in flight together.
 
 // Correctly rounded a / b for the operands of ln_unit (a in [-0.25, 0.5],
-// b in [1.75, 2.5]): the reciprocal refinement and the two residual
-// corrections of the full IEEE division sequence, without its range scaling
-// and special-value fix-up, which are identities for finite operands of
-// moderate exponent.  Every reachable operand pair is checked against the
-// correctly rounded quotient by the exhaustive transform test.
+// b in [1.75, 2.5]): one Newton-Raphson refinement of the hardware
+// reciprocal, then two quotient corrections from the exact FMA residual
+// a - b q (Markstein, IBM J. Res. Dev. 34(1), 1990).  No range scaling or
+// special-value handling is needed for finite operands of moderate exponent.
+// Every reachable operand pair is checked against the correctly rounded
+// quotient by the exhaustive transform test.
 template <int P>
 __device__ __forceinline__ void div_rn_moderate_n(const float (&a)[P], const float (&b)[P], float (&out)[P]) {
     float y[P], e[P], q[P], r[P];
@@ -149,7 +150,8 @@ __device__ __forceinline__ float div_rn_moderate(float a, float b) {
 
 // Correctly rounded sqrt(x) for finite normal x > 0 away from the denormal
 // range: the hardware estimate (within 1 ulp) is moved to a neighbour when the
-// exact residual x - s' s says that the neighbour is nearer.
+// exact FMA residual x - s' s says that the neighbour is nearer (the residual
+// test of Markstein's method).
 template <int P>
 __device__ __forceinline__ void sqrt_rn_normal_n(const float (&x)[P], float (&out)[P]) {
     float sq[P];

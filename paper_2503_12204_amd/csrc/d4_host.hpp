@@ -212,14 +212,16 @@ bool tile_override(int dyn, int n, int T, Tile* out);
 // any, else the shared rule.
 Tile batch_tile(int dyn, int n, int T);
 
-// Dynamic LDS of the cooperative kernel: controls [n][G][4][S] (G = Tb d_u / 4
-// + 1 Philox blocks per robot and time block), single-buffered positions
-// [Tb][2n-1][S] and masks [2][Tb][S]; the final reductions reuse the space.
+// Dynamic LDS of the cooperative kernel: double-buffered controls
+// [2][n][G][4][S] (G = Tb d_u / 4 + 1 Philox blocks per robot and time block,
+// plus two of padding for the rollout's read-ahead)
+// and positions [2][Tb][2n-1][S], triple-buffered masks [3][Tb][S]; the final
+// reductions reuse the space.
 inline size_t coop_lds(int dyn, size_t n, size_t S, size_t Tb, size_t R) {
     const Shape s = shape_of(dyn);
     const size_t slot = s.dp == 3 ? 16 : 8;
-    const size_t G = Tb * s.du / 4 + 1;
-    const size_t a = n * G * 4 * S * 4 + Tb * (2 * n - 1) * S * slot + 2 * Tb * S * 4;
+    const size_t G = Tb * s.du / 4 + 3;
+    const size_t a = 2 * n * G * 4 * S * 4 + 2 * Tb * (2 * n - 1) * S * slot + 3 * Tb * S * 4;
     const size_t b = (3 + R) * n * S * 4;
     return a > b ? a : b;
 }
@@ -227,12 +229,14 @@ inline size_t coop_lds(int dyn, size_t n, size_t S, size_t Tb, size_t R) {
 // Single-problem default: halve the samples per workgroup until there are at
 // least 256 workgroups (one per CU), then add replica lanes (cooperative
 // kernel), up to 16 and 1024 lanes per workgroup, when a workgroup would be
-// smaller.  The cooperative kernel's rollout runs on one replica between
-// barriers, so its time blocks are as long as the LDS allows (up to 64 steps).
+// smaller.  When the cooperative kernel pipelines its stages (replica 0 fills
+// whole waves) a horizon is cut into about five time blocks; otherwise its
+// stages run one after another and its time blocks are as long as the LDS
+// allows (up to 64 steps).
 // A single 3D problem with the full sample tile takes positions near 48 KiB
 // instead of 32 (at 16 robots Tb = 12 runs 0.7 % faster than 8); the batched
 // kernel keeps the shared rule, under which its mixed batches run fastest.
-inline Tile single_tile(int dyn, int n, int M) {
+inline Tile single_tile(int dyn, int n, int M, int T) {
     Tile t = default_tile(dyn, n);
     int S = t.S;
     while (S > 1 && (M + S - 1) / S < 256) S >>= 1;
@@ -248,7 +252,13 @@ inline Tile single_tile(int dyn, int n, int M) {
     const int slot = shape_of(dyn).dp == 3 ? 16 : 8;
     int Tb = std::max(cs, std::min(16, ((32 * 1024) / (n * S * slot)) / cs * cs));
     if (R > 1) {
-        Tb = 64;
+        if ((n * S) % 64 == 0) {
+            // pipelined stages: about five time blocks, of at least 16 steps
+            Tb = std::max(16, ((T + 4) / 5 + cs - 1) / cs * cs);
+        } else {
+            // sequential stages: time blocks as long as the LDS allows
+            Tb = 64;
+        }
         while (Tb > cs && coop_lds(dyn, n, S, Tb, R) > LDS_DYNAMIC_MAX) Tb -= cs;
     }
     Tile out;
@@ -260,7 +270,7 @@ inline Tile single_tile(int dyn, int n, int M) {
 
 inline Tile pick_tile(const d4_problem* p) {
     const int n = p->n_robots;
-    Tile t = single_tile(p->dyn, n, p->n_samples);
+    Tile t = single_tile(p->dyn, n, p->n_samples, p->horizon);
     Tile o;
     if (tile_override(p->dyn, n, p->horizon, &o)) t = o;
     int S = t.S, Tb = t.Tb;

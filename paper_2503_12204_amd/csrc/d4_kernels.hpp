@@ -78,6 +78,15 @@ __device__ __forceinline__ void stage_obstacles(const RollFitArgs& a, float4* ob
 }
 
 // Binary obstacle hit of a position: within the reward distance of any obstacle.
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
+template <int V>
+struct IntTag {
+    static constexpr int value = V;
+};
+
 template <int DP>
 __device__ __forceinline__ int obstacle_hit(const float* x, const float4* obs_l, int n_obs) {
     int hit = 0;
@@ -490,16 +499,19 @@ __global__ void __launch_bounds__(256) k_rollfit(const RollFitArgs a) {
 }
 
 // Cooperative variant of the fused kernel for problems with few (sample,
-// robot) lanes: R replica lanes per (sample, robot).  Per time block of Tb
-// steps: (1) all replicas generate the robot's draws of the block, whole
-// Philox blocks, write them to eps and turn them into the block's sampled
-// controls in LDS; (2) replica 0 rolls the robot out over the block, reading
-// its controls from LDS; (3) all replicas share the pair
-// checks, step tt going to replica tt mod R; (4) replica 0 reads the collision
-// masks.  Every value is computed as in the one-lane kernel and every sum is
-// taken in the same order, so the results are identical to it.
-// Lanes: tid = rep * (n*S) + k * S + ms.  LDS: controls [n][G][4][S] floats with
-// G = Tb*d_u/4 + 1, positions [Tb][2n-1][S] slots, masks [2][Tb][S].
+// robot) lanes: R >= 2 replica lanes per (sample, robot).  Per time block of
+// Tb steps: (1) the draws of the robot's block, whole Philox blocks, go to
+// eps and, as the block's sampled controls, to LDS; (2) replica 0 rolls the
+// robot out over the block, reading its controls from LDS; (3) the pair
+// checks, one step per replica in turn; (4) the collision masks are read.
+// Only the rollout is serial, so when replica 0 fills whole waves the stages
+// are pipelined over the blocks: the rollout of block i overlaps the draws of
+// block i+1 and the pair checks of block i-1; otherwise the blocks' stages run
+// one after another.  Every value is computed as in the one-lane kernel and
+// every sum is taken in the same order, so the results are identical to it.
+// Lanes: tid = rep * (n*S) + k * S + ms.  LDS: controls [2][n][G][4][S]
+// floats with G = Tb*d_u/4 + 3, positions [2][Tb][2n-1][S] slots, masks
+// [3][Tb][S].
 template <int DYN, int MODE>
 __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, int m0, float* lds) {
     using DY = Dyn<DYN>;
@@ -507,7 +519,9 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
     using PS = PosSlot<DP>;
     using PT = typename PS::T;
     const int n = a.n, T = a.T, M = a.M, S = a.S, Tb = a.Tb;
-    const int G = Tb * DU / 4 + 1;
+    // Philox blocks per robot and time block, plus two of padding that the
+    // rollout's read-ahead may touch (and never uses)
+    const int G = Tb * DU / 4 + 3;
     const int tid = threadIdx.x;
     const int group = n * S;
     const int rep = tid / group;
@@ -519,9 +533,10 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
     const bool live = active && m < M;
     const int mc = m < M ? m : M - 1;
     const int n2 = 2 * n - 1;
-    float* nz = lds;                                                           // [n][G][4][S]
-    PT* pos = reinterpret_cast<PT*>(nz + (size_t)n * G * 4 * S);              // [Tb][2n-1][S]
-    uint32_t* mask = reinterpret_cast<uint32_t*>(pos + (size_t)Tb * n2 * S); // [2][Tb][S]
+    const size_t NZB = (size_t)n * G * 4 * S, PB = (size_t)Tb * n2 * S;
+    float* nz = lds;                                                     // [2][n][G][4][S]
+    PT* pos = reinterpret_cast<PT*>(nz + 2 * NZB);                      // [2][Tb][2n-1][S]
+    uint32_t* mask = reinterpret_cast<uint32_t*>(pos + 2 * PB);         // [3][Tb][S]
 
     float x[DX], aux[DY::AUX], g[DP];
 #pragma unroll
@@ -551,82 +566,253 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
         uhi[d] = vgpr_copy(a.uhi[d]);
     }
     const float sigma = vgpr_copy(a.sigma), mscale = vgpr_copy(a.mean_scale);
-    const PhiloxKey pk = PhiloxKey::make<true>(a.key0, a.key1);
+    // the key schedule stays in SGPRs: the draws here are bound by latency,
+    // not by the half issue rate of an SGPR operand, and the kernel's 1024
+    // lanes leave each 128 VGPRs
+    const PhiloxKey pk = PhiloxKey::make<false>(a.key0, a.key1);
     const int jmax = active ? ((n - 1) >> 1) + ((((n & 1) == 0) && (k < (n >> 1))) ? 1 : 0) : 0;
     const bool pairs_mode = (a.flags & FLAG_SAFE_PAIRS) != 0;
     const size_t Ms = (size_t)M;
-    float* nzk = nz + (size_t)k * G * 4 * S + ms;
+    const size_t nzk_off = (size_t)k * G * 4 * S + ms;
 
     const int nblk = (T + Tb - 1) / Tb;
-    for (int b = 0; b < nblk; ++b) {
-        const int buf = b & 1;
-        const int t0 = b * Tb;
+    // (1) draws of time block bb into control buffer nzb, Philox blocks
+    // r0, r0 + rstride, ... of the robot's block range: the block's sampled
+    // controls go to LDS, its normals to eps.  The control bases of a Philox
+    // block are loaded one block ahead (the first block's by draw_bases,
+    // which the caller issues early), so their latency is covered.
+    struct DrawBlock {
+        uint32_t e_lo, e_hi, g_a;
+        int G_b;
+    };
+    auto draw_span = [&](int bb) {
+        DrawBlock db;
+        const int t0 = bb * Tb;
+        const int tcount = min(Tb, T - t0);
+        db.e_lo = ebase + (uint32_t)(t0 * DU);
+        db.e_hi = db.e_lo + (uint32_t)(tcount * DU);
+        db.g_a = db.e_lo >> 2;
+        db.G_b = (int)(((db.e_hi - 1) >> 2) - db.g_a) + 1;
+        return db;
+    };
+    // control bases of Philox block gi (indices clamped into the time block;
+    // the clamped values are not used)
+    auto draw_bases = [&](const DrawBlock& db, int gi, float (&ubj)[4], float (&duj)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t e = 4 * (db.g_a + (uint32_t)gi) + (uint32_t)j;
+            const uint32_t ec = e < db.e_lo ? db.e_lo : e >= db.e_hi ? db.e_hi - 1 : e;
+            ubj[j] = a.u_base[ec];
+            duj[j] = a.du_in[ec];
+        }
+    };
+    auto draw_block = [&](const DrawBlock& db, int nzb, int r0, int rstride, float (&ubj)[4], float (&duj)[4]) {
+        float* nzk = nz + nzb * NZB + nzk_off;
+        for (int gi = r0; gi < db.G_b; gi += rstride) {
+            float ubn[4], dun[4];
+            if (gi + rstride < db.G_b) draw_bases(db, gi + rstride, ubn, dun);
+            float z[4];
+            normal_blocks<1, true>(db.g_a + (uint32_t)gi, (uint32_t)mc, c2, a.inst, pk, z);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t e = 4 * (db.g_a + (uint32_t)gi) + (uint32_t)j;
+                const bool in_blk = e >= db.e_lo && e < db.e_hi;
+                float v = z[j];
+                if (in_blk) {
+                    const int d = (int)((e - ebase) % (uint32_t)DU);
+                    // the bounds are chosen by selects of values (an indexed
+                    // choice would put the two small arrays in scratch memory)
+                    float lo = ulo[0], hi = uhi[0];
+                    if constexpr (DU > 1) {
+                        lo = d == 1 ? ulo[1] : lo;
+                        hi = d == 1 ? uhi[1] : hi;
+                    }
+                    if constexpr (DU > 2) {
+                        lo = d == 2 ? ulo[2] : lo;
+                        hi = d == 2 ? uhi[2] : hi;
+                    }
+                    v = sample_control(ubj[j], duj[j], mscale, sigma, z[j], lo, hi);
+                }
+                nzk[(size_t)(gi * 4 + j) * S] = v;
+                if (live && in_blk) a.eps[(size_t)e * Ms + m] = z[j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ubj[j] = ubn[j];
+                duj[j] = dun[j];
+            }
+        }
+    };
+    // (2) rollout of time block bb from control buffer nzb into position
+    // buffer pb.  Step tt's control d sits at nzk[(o + tt d_u + d) S] with
+    // o = e_lo mod 4 (the block's draws start at Philox block e_lo / 4).  The
+    // controls are read two steps ahead of their use (the two padding blocks
+    // hold the reads past the block's end), before the position stores that
+    // the compiler may not move them past, so no LDS round trip sits in the
+    // state chain.  The loop body has no branch (robot n-1's second position
+    // store repeats its first), so the unrolled steps are one block of
+    // straight-line code that the scheduler can interleave.  The goal and
+    // obstacle terms, which need the positions only, are left to another
+    // replica.
+    auto roll_block = [&](int bb, int nzb, int pb, auto score_tag) {
+        // SCORE 0: positions only; 1: goal terms inline; 2: goal and obstacle terms inline
+        constexpr int SCORE = decltype(score_tag)::value;
+        const int t0 = bb * Tb;
         const int tcount = min(Tb, T - t0);
         const uint32_t e_lo = ebase + (uint32_t)(t0 * DU);
-        const uint32_t e_hi = e_lo + (uint32_t)(tcount * DU);
-        const uint32_t g_a = e_lo >> 2;
-        const int G_b = (int)(((e_hi - 1) >> 2) - g_a) + 1;
-        // (1) draws of this block, and from them the block's sampled controls:
-        // the replicas read the control bases in parallel, so the rollout's
-        // serial step chain holds no global load (LDS keeps u; eps gets z)
-        if (active) {
-            for (int gi = rep; gi < G_b; gi += R) {
-                float z[4];
-                normal_blocks<1, true>(g_a + (uint32_t)gi, (uint32_t)mc, c2, a.inst, pk, z);
+        const float* ub = nz + nzb * NZB + nzk_off + (size_t)(e_lo & 3u) * S;
+        PT* slot = pos + pb * PB + k * S + ms;   // step tt at slot + tt (2n-1) S
+        const int dup = k < n - 1 ? n * S : 0;
+        float u1[DU], u2[DU];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t e = 4 * (g_a + (uint32_t)gi) + (uint32_t)j;
-                    const bool in_blk = e >= e_lo && e < e_hi;
-                    float v = z[j];
-                    if (in_blk) {
-                        const int d = (int)((e - ebase) % (uint32_t)DU);
-                        const float lo = d == 0 ? ulo[0] : d == 1 ? ulo[DU > 1 ? 1 : 0] : ulo[DU - 1];
-                        const float hi = d == 0 ? uhi[0] : d == 1 ? uhi[DU > 1 ? 1 : 0] : uhi[DU - 1];
-                        v = sample_control(a.u_base[e], a.du_in[e], mscale, sigma, z[j], lo, hi);
-                    }
-                    nzk[(size_t)(gi * 4 + j) * S] = v;
-                    if (live && in_blk) a.eps[(size_t)e * Ms + m] = z[j];
+        for (int d = 0; d < DU; ++d) {
+            u1[d] = ub[(size_t)d * S];
+            u2[d] = ub[(size_t)(DU + d) * S];
+        }
+        ub += (size_t)2 * DU * S;
+        // four steps per unrolled body (two for the six-state 3D model, which
+        // would otherwise exceed the 128 VGPRs of a 1024-lane workgroup)
+        constexpr int RU = DX > 4 ? 2 : 4;
+#pragma unroll RU
+        for (int tt = 0; tt < tcount; ++tt) {
+            float u[DU];
+#pragma unroll
+            for (int d = 0; d < DU; ++d) {
+                u[d] = u1[d];
+                u1[d] = u2[d];
+                u2[d] = ub[(size_t)d * S];
+            }
+            ub += (size_t)DU * S;
+            DY::step(x, aux, u, a.sc);
+            if constexpr (SCORE >= 1) goal_acc += goal_term(fast_sqrt(goal_d2<DP>(x, g)), inv_d0);
+            if constexpr (SCORE == 2) obs_cnt += obstacle_hit<DP>(x, obs_l, n_obs);
+            const PT v = PS::pack(x);
+            slot[0] = v;
+            slot[dup] = v;
+            slot += n2 * S;
+        }
+    };
+    // goal and obstacle terms of time block bb from position buffer pb, in
+    // step order (the goal sum is taken in the one-lane kernel's order); the
+    // positions of four steps are read together
+    auto score_block = [&](int bb, int pb, auto obs_tag) {
+        constexpr bool OBS = decltype(obs_tag)::value;
+        const int tcount = min(Tb, T - bb * Tb);
+        const PT* slot = pos + pb * PB + k * S + ms;
+        const int st = n2 * S;
+        for (int tt0 = 0; tt0 < tcount; tt0 += 4) {
+            float xp[4][DP];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int tt = tt0 + q < tcount ? tt0 + q : tcount - 1;
+                PS::unpack(slot[tt * st], xp[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (tt0 + q < tcount) {
+                    goal_acc += goal_term(fast_sqrt(goal_d2<DP>(xp[q], g)), inv_d0);
+                    if constexpr (OBS) obs_cnt += obstacle_hit<DP>(xp[q], obs_l, n_obs);
                 }
             }
+        }
+    };
+    // (3) pair checks of time block bb on position buffer pb, steps r0,
+    // r0 + rstride, ...: hits OR-ed into the step's collision mask in mask
+    // buffer mb for both robots
+    auto pair_block = [&](int bb, int pb, int mb, int r0, int rstride) {
+        const int tcount = min(Tb, T - bb * Tb);
+        for (int tt = r0; tt < tcount; tt += rstride) {
+            const uint32_t bits = pair_bits<DP>(pos + pb * PB + tt * n2 * S + ms, n, S, k, jmax, a.thr2);
+            hit_cnt += __popc(bits);
+            if (bits) atomicOr(&mask[(mb * Tb + tt) * S + ms], bits | (1u << k));
+        }
+    };
+    // (4) collision flags of robot k in time block bb
+    auto mask_read = [&](int bb, int mb) {
+        const int tcount = min(Tb, T - bb * Tb);
+        for (int tt = 0; tt < tcount; ++tt) safe_cnt += (mask[(mb * Tb + tt) * S + ms] >> k) & 1u;
+    };
+
+    if ((group & 63) != 0) {
+        // Sequential schedule, for workgroups whose replica 0 does not fill
+        // whole waves (the roles would share waves, and a pipeline would only
+        // add stages): per block, the draws on every replica, the rollout
+        // with its goal and obstacle terms on replica 0, the pair checks on
+        // every replica, the masks read by replica 1 (mask buffers alternate
+        // so that clearing the next one does not race with that read).
+        for (int b = 0; b < nblk; ++b) {
+            if (active) {
+                const DrawBlock db = draw_span(b);
+                float ubj[4], duj[4];
+                if (rep < db.G_b) draw_bases(db, rep, ubj, duj);
+                draw_block(db, 0, rep, R, ubj, duj);
+            }
+            if (rep == 0 && k == 0 && active)
+                for (int tt = 0; tt < Tb; ++tt) mask[((b & 1) * Tb + tt) * S + ms] = 0u;
+            __syncthreads();
+            if (rep == 0 && active) {
+                if (n_obs) roll_block(b, 0, 0, IntTag<2>{});
+                else roll_block(b, 0, 0, IntTag<1>{});
+            }
+            __syncthreads();
+            if (active) pair_block(b, 0, b & 1, rep, R);
+            __syncthreads();
+            if (rep == 1 && active) mask_read(b, b & 1);
+        }
+    } else {
+        // Software pipeline over the time blocks, one barrier per stage.  In
+        // stage i replica 0 rolls block i out, at raised wave priority; the
+        // workers (replicas 2..R-1, or replica 1 when R = 2) check the pairs
+        // of block i-1 and draw block i+1; replica 1 scores block i-1, reads
+        // the collision masks of block i-2 and clears the mask buffer read in
+        // the stage before.  Controls and positions are double-buffered,
+        // masks triple-buffered.
+        if (active) {
+            const DrawBlock db = draw_span(0);
+            float ubj[4], duj[4];
+            if (rep < db.G_b) draw_bases(db, rep, ubj, duj);
+            draw_block(db, 0, rep, R, ubj, duj);
         }
         if (rep == 0 && k == 0 && active)
-            for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
+            for (int q = 0; q < 3 * Tb; ++q) mask[q * S + ms] = 0u;
         __syncthreads();
-        // (2) rollout of the block by replica 0 (unrolled, so that the next
-        // steps' control reads run ahead of the state chain)
-        if (rep == 0 && active) {
-#pragma unroll 4
-            for (int tt = 0; tt < tcount; ++tt) {
-                const int t = t0 + tt;
-                float u[DU];
-#pragma unroll
-                for (int d = 0; d < DU; ++d) {
-                    const uint32_t e = ebase + (uint32_t)(t * DU + d);
-                    u[d] = nzk[(size_t)(((e >> 2) - g_a) * 4 + (e & 3u)) * S];
+        const int w0 = R > 2 ? 2 : 1, workers = R - w0;
+        for (int i = 0; i <= nblk + 1; ++i) {
+            if (active) {
+                if (rep == 0) {
+                    if (i < nblk) {
+                        __builtin_amdgcn_s_setprio(2);
+                        roll_block(i, i & 1, i & 1, IntTag<0>{});
+                        __builtin_amdgcn_s_setprio(0);
+                    }
+                } else {
+                    if (rep >= w0) {
+                        // the draws' first control bases are requested before
+                        // the pair checks, which then cover their latency
+                        const bool draw = i + 1 < nblk;
+                        const DrawBlock db = draw_span(draw ? i + 1 : 0);
+                        float ubj[4], duj[4];
+                        if (draw && rep - w0 < db.G_b) draw_bases(db, rep - w0, ubj, duj);
+                        if (i >= 1 && i <= nblk) pair_block(i - 1, (i - 1) & 1, (i - 1) % 3, rep - w0, workers);
+                        if (draw) draw_block(db, (i + 1) & 1, rep - w0, workers, ubj, duj);
+                    }
+                    if (rep == 1) {
+                        if (i >= 1 && i <= nblk) {
+                            if (n_obs) score_block(i - 1, (i - 1) & 1, BoolTag<true>{});
+                            else score_block(i - 1, (i - 1) & 1, BoolTag<false>{});
+                        }
+                        if (i >= 2) mask_read(i - 2, (i - 2) % 3);
+                        if (i >= 3 && k == 0)
+                            for (int tt = 0; tt < Tb; ++tt) mask[((i % 3) * Tb + tt) * S + ms] = 0u;
+                    }
                 }
-                DY::step(x, aux, u, a.sc);
-                goal_acc += goal_term(fast_sqrt(goal_d2<DP>(x, g)), inv_d0);
-                if (n_obs) obs_cnt += obstacle_hit<DP>(x, obs_l, n_obs);
-                const PT v = PS::pack(x);
-                PT* slot = pos + (tt * n2 + k) * S + ms;
-                slot[0] = v;
-                if (k < n - 1) slot[n * S] = v;
             }
+            __syncthreads();
         }
-        __syncthreads();
-        // (3) pair checks shared by the replicas
-        if (active) {
-            for (int tt = rep; tt < tcount; tt += R) {
-                const uint32_t bits = pair_bits<DP>(pos + tt * n2 * S + ms, n, S, k, jmax, a.thr2);
-                hit_cnt += __popc(bits);
-                if (bits) atomicOr(&mask[(buf * Tb + tt) * S + ms], bits | (1u << k));
-            }
-        }
-        __syncthreads();
-        // (4) collision flags of robot k
-        if (rep == 0 && active)
-            for (int tt = 0; tt < tcount; ++tt) safe_cnt += (mask[(buf * Tb + tt) * S + ms] >> k) & 1u;
     }
+    // The roles change only which lane evaluates a value, never its
+    // operations or their order, so the results are those of the one-lane
+    // kernel under either schedule.
 
     __syncthreads();
     float* rg = lds;
@@ -635,11 +821,14 @@ __device__ __forceinline__ void rollfit_coop_tile(const RollFitArgs& a, int R, i
     int* ro = rh + R * group;              // [n][S]
     if (active) {
         rh[rep * group + k * S + ms] = hit_cnt;
-        if (rep == 0) {
+        // the goal and obstacle sums are replica 0's under the sequential
+        // schedule and replica 1's under the pipeline; the masks are read by
+        // replica 1 under both
+        if (rep == ((group & 63) != 0 ? 0 : 1)) {
             rg[k * S + ms] = goal_acc;
-            rs[k * S + ms] = safe_cnt;
             ro[k * S + ms] = obs_cnt;
         }
+        if (rep == 1) rs[k * S + ms] = safe_cnt;
     }
     __syncthreads();
     if (rep == 0 && k == 0 && live) {
