@@ -108,13 +108,16 @@ def test_tile_rule_without_a_gpu():
     S = min(64, 256 / n), halved until M / S >= 256; with the full S the time
     block keeps the positions near 32 KiB (2D, 8-byte slots), or near 48 KiB
     for a single 3D problem (16-byte slots); with a halved S, R = min(16,
-    1024 / (S n)) replica lanes and the longest block that fits (up to 64)."""
+    1024 / (S n)) replica lanes, and time blocks of about a fifth of the
+    horizon (at least 16 steps) when replica 0 fills whole waves (n S a
+    multiple of 64, the pipelined schedule), else the longest block that
+    fits (up to 64)."""
     import bench
     from paper_2503_12204_amd import autotune as AT
     expect = {
         # name: (single problem, batched rule)
         "holo3d_sphere_swap": ((16, 12, 1), (16, 8, 1)),     # 48 KiB / (16 * 16 * 16 B) = 12
-        "unicycle_random": ((8, 64, 16), (32, 16, 1)),       # M = 2048: S 32 -> 8, R = 1024 / 64
+        "unicycle_random": ((8, 20, 16), (32, 16, 1)),       # M = 2048: S 32 -> 8, R = 1024 / 64, T / 5
         "holo2d_circle_swap": ((1, 64, 16), (64, 16, 1)),    # M = 256: S 64 -> 1, R = 16
         "diffdrive_circle_swap": ((16, 16, 1), (16, 16, 1)),  # 32 KiB / (16 * 16 * 8 B) = 16
         "holo2d_circle_obstacles": ((16, 16, 1), (16, 16, 1)),
