@@ -143,58 +143,82 @@ def _candidates(bucket):
     return out
 
 
-def tune_batch(probs, x0s, goals, path=DEFAULT_CACHE, steps=10, min_tiles=1024, force=False, log=None):
-    """Tile of every (dynamics, team-size, horizon) bucket of a batch, chosen by
-    timing short whole batched iterations (`steps` denoising steps, so the
-    timing covers the step sequence and not one step) of a sub-batch of the
-    batch's own instances in that bucket, repeated under new instance ids
-    until one launch holds at least `min_tiles` reward tiles (so that the
-    sub-batch fills the GPU as the whole batch does), with each candidate
-    tile; cached per architecture and kernel source version, and installed
-    with d4_batch_tile_set, which refuses tiles whose LDS would lower the
-    whole batch's occupancy.  A tile changes only speed.  Returns
-    {bucket: entry}."""
+def _batch_cost(p):
+    """Relative cost of one instance: its pair checks and its draws."""
+    return p.n_robots * p.horizon * p.n_samples * (p.n_robots + 40 * p.du)
+
+
+def tune_batch(probs, x0s, goals, path=DEFAULT_CACHE, steps=None, reps=1, min_gain=0.01, min_share=0.05,
+               force=False, log=None):
+    """Tiles of the (dynamics, team-size, horizon) buckets of a batch, chosen
+    by coordinate descent on the time of the whole batch: starting from the
+    shared rule (which sizes each instance's sample tile by its own team), each
+    bucket holding at least `min_share` of the batch's work tries every
+    admissible candidate tile in turn, the others held fixed, and keeps one
+    only when a batched iteration (the least of `reps` timed iterations, after
+    one untimed) runs at least `min_gain` faster than the best so far.  The
+    iterations keep the problems' own denoising steps unless `steps` is
+    given: a shorter schedule changes how close the sampled trajectories come,
+    and with it the share of the pair checks, so it ranks tiles differently.  The result can therefore not be slower than the rule by more than the
+    timing noise.  A tile changes only speed (d4_batch_tile_set refuses tiles
+    whose LDS would lower the whole batch's occupancy).  Cached per
+    architecture, kernel source version and batch composition.  Returns
+    {bucket: entry} for the buckets that left the rule."""
     import time
-    import numpy as np
-    cache = _load(path)
     groups = {}
     for j, p in enumerate(probs):
         groups.setdefault(batch_bucket(p), []).append(j)
+    comp = hashlib.sha256(json.dumps(sorted((list(b), len(v)) for b, v in groups.items())).encode()).hexdigest()[:16]
+    key = f"{_arch()}|{source_version()}|batch|{comp}|M{probs[0].n_samples}|N{steps or probs[0].n_steps}"
+    cache = _load(path)
+    for b in groups:
+        clear_batch_tile(b)
+    if key in cache and not force:
+        chosen = {tuple(e["bucket"]): e for e in cache[key]}
+        for b, e in chosen.items():
+            set_batch_tile(b, e["S"], e["Tb"])
+        return chosen
+    sub = [p.replace(n_steps=steps) for p in probs] if steps else list(probs)
+
+    def measure():
+        bc = L.BatchContext(sub, x0s, goals)
+        bc.iterate(0)
+        torch.cuda.synchronize()
+        best_t = None
+        for k in range(reps):
+            t0 = time.perf_counter()
+            bc.iterate(1 + k)
+            dt = time.perf_counter() - t0
+            best_t = dt if best_t is None else min(best_t, dt)
+        bc.close()
+        return best_t
+
+    total = sum(_batch_cost(p) for p in probs)
+    share = {b: sum(_batch_cost(probs[j]) for j in idx) / total for b, idx in groups.items()}
+    best = measure()
+    if log:
+        log(f"batch tuner: rule tiles {best * 1e3:.2f} ms per iteration")
     chosen = {}
-    for bucket, idx in sorted(groups.items()):
-        key = f"{_arch()}|{source_version()}|batch|" + "|".join(str(v) for v in bucket) + f"|M{probs[0].n_samples}"
-        if key in cache and not force:
-            e = cache[key]
-            set_batch_tile(bucket, e["S"], e["Tb"])
-            chosen[bucket] = e
+    for b in sorted(groups, key=lambda b: -share[b]):
+        if share[b] < min_share:
             continue
-        S_rule = min(64, 256 // bucket[2])
-        tiles_each = -(-probs[0].n_samples // S_rule)
-        reps = -(-min_tiles // (tiles_each * len(idx)))
-        sel = [idx[i % len(idx)] for i in range(len(idx) * max(1, reps))]
-        sub = [probs[j].replace(n_steps=steps, instance_id=r) for r, j in enumerate(sel)]
-        best = None
-        for S, Tb in _candidates(bucket):
+        for S, Tb in _candidates(b):
             try:
-                set_batch_tile(bucket, S, Tb)
+                set_batch_tile(b, S, Tb)
             except L.D4Error:
                 continue
-            bc = L.BatchContext(sub, [x0s[j] for j in sel], [goals[j] for j in sel])
-            bc.iterate(0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(2):
-                bc.iterate(1 + k, sync=False)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) / 2 * 1e3
-            bc.close()
-            if best is None or ms < best["ms"]:
-                best = {"S": S, "Tb": Tb, "ms": ms, "instances": len(sel)}
-        set_batch_tile(bucket, best["S"], best["Tb"])
-        chosen[bucket] = best
-        cache[key] = best
-        if log:
-            log(f"bucket {bucket}: S={best['S']} Tb={best['Tb']} ({best['ms']:.2f} ms for {len(sel)} instances)")
+            t = measure()
+            kept = t < best * (1.0 - min_gain)
+            if kept:
+                best = t
+                chosen[b] = {"bucket": list(b), "S": S, "Tb": Tb, "ms": t * 1e3, "share": share[b]}
+            if log:
+                log(f"batch tuner: bucket {b} S={S} Tb={Tb}: {t * 1e3:.2f} ms{' (kept)' if kept else ''}")
+        if b in chosen:
+            set_batch_tile(b, chosen[b]["S"], chosen[b]["Tb"])
+        else:
+            clear_batch_tile(b)
+    cache[key] = list(chosen.values())
     os.makedirs(os.path.dirname(path), exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as fh:

@@ -49,9 +49,9 @@ def _time_batch(L, inst, iterations):
 def batched_vs_plain(L, count=512, n_samples=1024, iterations=2, seed=0, plain=True, tune=True, log=print):
     """The batched form against the same instances run one after another
     through the single-problem path.  With tune, the batch's bucket tiles are
-    first chosen by timing short batched iterations (autotune.tune_batch; the
-    tuning time is reported, not counted), and the rule's tiles are timed as
-    well."""
+    also chosen by coordinate descent on the time of short whole-batch
+    iterations (autotune.tune_batch, starting from the rule; the tuning time
+    is reported, not counted), and the batch is timed with them."""
     from . import autotune as AT
     inst = W.batched_mix(count=count, n_samples=n_samples, seed=seed)
     probs = [p for p, _, _ in inst]
@@ -70,12 +70,12 @@ def batched_vs_plain(L, count=512, n_samples=1024, iterations=2, seed=0, plain=T
                                   path=f"{td}/tiles.json", log=log)
         t_tune = time.perf_counter() - t0
         t_batch = _time_batch(L, inst, iterations)
-        for b in tuned:
+        for b in {AT.batch_bucket(p) for p in probs}:
             AT.clear_batch_tile(b)
         log(f"batched, tuned tiles ({t_tune:.1f} s of tuning): {t_batch * 1e3:.1f} ms per iteration")
     head = {"instances": count, "samples": n_samples, "batched_ms_per_iteration": t_batch * 1e3,
             "batched_rule_tiles_ms_per_iteration": t_rule * 1e3,
-            "tuned_tiles": {"/".join(str(v) for v in b): e for b, e in tuned.items()} if tuned else None,
+            "tuned_tiles": {"/".join(str(v) for v in b): e for b, e in tuned.items()} if tuned is not None else None,
             "batched_robot_step_samples_per_s": units / t_batch, "algorithmic_ops_per_step": ops_per_step,
             "step_algorithmic_rate_T_per_s": ops_per_step * probs[0].n_steps / t_batch / 1e12}
     if not plain:

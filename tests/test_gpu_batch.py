@@ -215,8 +215,9 @@ def test_persistent_step_equals_two_launch_form(L):
 def test_bucket_tiles_change_speed_only(L):
     """Tiles installed per (dynamics, team size, horizon) bucket for the
     batched form (what autotune.tune_batch installs) give the same plans and
-    statistics as the rule's tiles; the tuner itself runs on a small batch
-    and leaves every bucket it chose installed and admissible."""
+    statistics as the rule's tiles; the tuner itself runs on a small batch,
+    leaves every bucket it chose installed and the others on the rule, and a
+    second call with the same batch installs the cached choice."""
     from paper_2503_12204_amd import autotune as AT
     inst = _mix(12, 128, 6, seed=13, t_range=(9, 50))
     probs = [p for p, _, _ in inst]
@@ -241,16 +242,25 @@ def test_bucket_tiles_change_speed_only(L):
         for b in buckets:
             AT.clear_batch_tile(b)
         import tempfile
+        rule = {id(p): AT.get_tile(p, batched=True) for p in probs}
         with tempfile.TemporaryDirectory() as td:
-            chosen = AT.tune_batch(probs, [x for _, x, _ in inst], [g for _, _, g in inst], path=f"{td}/t.json",
-                                   steps=3, min_tiles=64)
-        assert set(chosen) == set(buckets)
-        for p in probs:
-            S, Tb, R = AT.get_tile(p, batched=True)
-            e = chosen[AT.batch_bucket(p)]
-            assert (S, Tb, R) == (e["S"], e["Tb"], 1)
-        u, st = run()
-        assert np.array_equal(u, ref_u) and st == ref_st
+            x0s, goals = [x for _, x, _ in inst], [g for _, _, g in inst]
+            chosen = AT.tune_batch(probs, x0s, goals, path=f"{td}/t.json", steps=3, min_share=0.0)
+            assert set(chosen) <= set(buckets)
+
+            def check():
+                for p in probs:
+                    e = chosen.get(AT.batch_bucket(p))
+                    want = rule[id(p)] if e is None else (e["S"], e["Tb"], 1)
+                    assert AT.get_tile(p, batched=True) == want
+            check()
+            u, st = run()
+            assert np.array_equal(u, ref_u) and st == ref_st
+            for b in buckets:
+                AT.clear_batch_tile(b)
+            again = AT.tune_batch(probs, x0s, goals, path=f"{td}/t.json", steps=3, min_share=0.0)
+            assert {b: (e["S"], e["Tb"]) for b, e in again.items()} == {b: (e["S"], e["Tb"]) for b, e in chosen.items()}
+            check()
     finally:
         for b in buckets:
             AT.clear_batch_tile(b)
