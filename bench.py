@@ -322,11 +322,13 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="only launch the fused kernel this many times (for counter runs)")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
-    ap.add_argument("--experiment", choices=["batched", "proposal", "sensitivity", "first_success", "gemm"],
+    ap.add_argument("--experiment", choices=["batched", "proposal", "sensitivity", "first_success", "gemm", "goal_gap"],
                     default=None,
                     help="time-to-target of the batched or learned-proposal form against the plain planner, "
                          "or the success-rate sweep over denoising steps and iterations")
     ap.add_argument("--runs", type=int, default=30, help="runs per cell of the sensitivity sweep")
+    ap.add_argument("--success-runs", type=int, default=50, help="runs per scenario of first_success")
+    ap.add_argument("--scenarios", default="circle,random", help="scenarios of first_success")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched experiment: time the batched form only (for profiling runs)")
     ap.add_argument("--no-tune", action="store_true",
@@ -379,15 +381,23 @@ def main():
                                 "frac": head["frac_of_peak"], "traffic": None},
                    "details": res}
         elif args.experiment == "first_success":
-            res = [E.first_success(L, scenario=sc, n=t, radius=args.radius or 4.0, log=log)
-                   for sc in ("circle", "random") for t in (int(x) for x in args.teams.split(","))]
+            res = [E.first_success(L, scenario=sc, n=t, radius=args.radius or 4.0, runs=args.success_runs, log=log)
+                   for sc in args.scenarios.split(",") for t in (int(x) for x in args.teams.split(","))]
             head = [r for r in res if r["scenario"] == "circle" and r["robots"] == 16] or res
             out = {"metric": "mean wall time to the first conflict-free plan, 16 robots 2D holonomic, antipodal circle",
                    "value": head[0]["mean_seconds_to_first_success"], "unit": "s", "n_gpus": 1,
                    "higher_is_better": False, "dtype": "f32", "data": "synthetic",
-                   "config": {"workload": "first_success", "description": "2D holonomic teams, antipodal circle and "
-                              "random targets in a square of the circle's diameter, T=100, M=2048, N=100, "
-                              "5 s deadline, 50 runs each"},
+                   "config": {"workload": "first_success", "description": "2D holonomic teams, antipodal circle of "
+                              f"radius {args.radius or 4.0} m and random targets in a square of the circle's diameter, "
+                              f"T=100, M=2048, N=100, 5 s deadline, {args.success_runs} runs each"},
+                   "details": res}
+        elif args.experiment == "goal_gap":
+            res = E.goal_gap(L, radius=args.radius or 4.0, log=log)
+            out = {"metric": "mean final distance to goal after 20 iterations, 16 robots 2D holonomic, antipodal circle",
+                   "value": res[0]["by_iteration"][-1]["mean_m"], "unit": "m", "n_gpus": 1,
+                   "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": "goal_gap", "description": f"antipodal circle of radius {args.radius or 4.0} m, "
+                              "T=100, M=2048, N=100, and variants of lambda, T and N"},
                    "details": res}
         elif args.experiment == "sensitivity":
             res = E.sensitivity(L, dynamics=tuple(args.dynamics.split(",")),

@@ -287,6 +287,71 @@ def sensitivity(L, dynamics=("diffdrive", "holo2d", "holo3d"), teams=(10, 16), s
             "denoising_steps": list(steps), "teams": list(teams), "dynamics": list(dynamics), "cells": cells}
 
 
+def goal_gap(L, n=16, radius=4.0, n_samples=2048, iterations=20, log=print):
+    """Why the plans stop short of their goals (the terminal condition of
+    Eqs. problem-conditions, read as every robot within goal_tol at t = T).
+    Algorithm 2 from zero controls on the 16-robot antipodal circle (2D
+    holonomic, M = 2048), once with the workload's settings and once each with
+    a sharper or flatter softmax (lambda), a longer horizon and more
+    denoising steps; after every iteration the plan's own trajectory gives each robot's
+    final distance to its goal.  Returns per variant the distances (mean,
+    median, max over robots) and the conflict-free and at-goal flags by
+    iteration."""
+    variants = [("workload settings (lambda 0.1, T 100, N 100)", {}),
+                ("lambda 0.01", {"temperature": 0.01}),
+                ("lambda 0.3", {"temperature": 0.3}),
+                ("lambda 1", {"temperature": 1.0}),
+                ("lambda 3", {"temperature": 3.0}),
+                ("T 150", {"horizon": 150}),
+                ("N 300", {"n_steps": 300})]
+    out = []
+    for label, kw in variants:
+        T = kw.get("horizon", 100)
+        p, x0, g = W.holo2d_circle(n=n, horizon=T, n_samples=n_samples, radius=radius,
+                                   n_steps=kw.get("n_steps", 100))
+        if "temperature" in kw:
+            p = p.replace(temperature=kw["temperature"])
+        x0_d, g_d = L._f32(x0), L._f32(g)
+        u = torch.zeros((p.n_robots, p.horizon, p.du), dtype=torch.float32, device="cuda")
+        traj = torch.empty((p.n_robots, p.horizon + 1, p.dx), dtype=torch.float32, device="cuda")
+        ctx = L.Context(p)
+        rows = []
+        try:
+            for k in range(iterations):
+                st = ctx.denoise_iter(x0_d, g_d, u, k, traj=traj)
+                d = np.linalg.norm(traj[:, -1, :p.dp].cpu().numpy().astype(np.float64) - g, axis=1)
+                rows.append({"iteration": k + 1, "mean_m": float(d.mean()), "median_m": float(np.median(d)),
+                             "max_m": float(d.max()), "within_tol": float((d <= p.goal_tol).mean()),
+                             "success": bool(st["success"]), "at_goal": bool(st["at_goal"]),
+                             "reward": float(st["reward"])})
+        finally:
+            ctx.close()
+        # one more iteration from the final plan through the split calls, not
+        # applied: the softmax weights' effective sample count (sum w)^2 /
+        # sum w^2 at the first, middle and last denoising steps, and the size
+        # of the deformation the iteration would add
+        du = torch.zeros(p.D, dtype=torch.float32, device="cuda")
+        ub = u.reshape(-1).contiguous()
+        ess = {}
+        for i in range(p.n_steps, 0, -1):
+            eps, r, _ = L.sample_rollout_fitness(p, x0_d, g_d, ub, du, iterations, i)
+            du, w = L.score_update(p, r, eps, du, i)
+            if i in (p.n_steps, p.n_steps // 2, 1):
+                w64 = w.double()
+                ess[i] = float(w64.sum() ** 2 / (w64 * w64).sum())
+        dU_rms = float(du.double().pow(2).mean().sqrt())
+        last = rows[-1]
+        log(f"{label}: after {iterations} iterations final distance mean {last['mean_m']:.3f} m, "
+            f"max {last['max_m']:.3f} m, robots within {p.goal_tol} m {last['within_tol']:.2f}, "
+            f"conflict-free {last['success']}")
+        log(f"  next iteration: effective samples {', '.join(f'step {i}: {v:.1f}' for i, v in ess.items())}; "
+            f"deformation rms {dU_rms:.3f}")
+        out.append({"variant": label, "goal_tol": p.goal_tol, "by_iteration": rows,
+                    "next_iteration_effective_samples": {str(i): v for i, v in ess.items()},
+                    "next_iteration_deformation_rms": dU_rms})
+    return out
+
+
 def first_success(L, scenario="circle", n=16, runs=50, n_samples=2048, horizon=100, n_steps=100, radius=4.0,
                   deadline_s=5.0, max_iterations=500, seed=0, log=print):
     """Wall time to the first conflict-free plan (Sec. V-C, the paper's
