@@ -16,7 +16,8 @@ The JSON line also carries:
                 78.6 T lane-operations/s (157.3 TFLOP/s counting an FMA as
                 two); the peak of the kernel's own instruction mix is a
                 secondary figure.
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload,
+                on every host core this process may use (at most 16).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -144,35 +145,58 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(name, target_s=10.0):
-    """The oracle, untouched, on a bounded sample: sampling, rollout, reward
-    and the weighted update of one denoising step for the first S samples,
-    repeated over consecutive steps until about target_s seconds of CPU work."""
+def _oracle_shard(job):
+    """One CPU worker of cpu_baseline: the oracle, untouched and single-
+    threaded, on samples [lo, hi) of consecutive denoising steps for about
+    target_s seconds.  Returns (robot*step*samples, seconds, steps)."""
+    name, lo, hi, target_s = job
+    from threadpoolctl import threadpool_limits
     from oracle import mbd as ombd
     from oracle import schedule as osched
     p, x0, g = make_workload(name)
-    S = min(p.n_samples, 1024)
     sched = osched.step_scalars(p.n_steps, p.beta_min, p.beta_max)
     ms, sg, os_ = sched
     du = np.zeros(p.D)
     ub = np.zeros(p.D)
-    from threadpoolctl import threadpool_limits
     steps = 0
     i = p.n_steps
     with threadpool_limits(limits=1):  # one core, whatever BLAS the oracle's NumPy would use
         t0 = time.perf_counter()
         while True:
-            out = ombd.sample_rewards(p, x0, g, ub, du, 0, i, sched=sched, samples=np.arange(S))
+            out = ombd.sample_rewards(p, x0, g, ub, du, 0, i, sched=sched, samples=np.arange(lo, hi))
             du, _ = ombd.mc_update(du, out["eps"], out["r"], ms[i], sg[i], os_[i], p.temperature, True)
             steps += 1
             i -= 1
             if time.perf_counter() - t0 >= target_s or i == 0:
                 break
         dt = time.perf_counter() - t0
-    units = p.n_robots * p.horizon * S * steps
-    return {"value": units / dt, "unit": "robot*step*samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} denoising steps of {name} restricted to samples 0..{S - 1} "
-                      f"(sampling, FP64 rollout, reward, weighted update), {dt:.1f} s, single-threaded NumPy"}
+    return p.n_robots * p.horizon * (hi - lo) * steps, dt, steps
+
+
+def cpu_baseline(name, target_s=10.0, workers=None):
+    """The oracle, untouched, on a bounded sample of the workload, on every
+    host core this process may use (at most 16): worker w runs sampling,
+    rollout, reward and the weighted update of consecutive denoising steps on
+    its own slice of the first min(M, 1024 W) samples, single-threaded, for
+    about target_s seconds; the rate is the workers' total work over the
+    longest worker's time.  The workers are forked processes that run only
+    NumPy (no GPU call)."""
+    import multiprocessing as mp
+    p, _, _ = make_workload(name)
+    W = workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    total = min(p.n_samples, 1024 * W)
+    W = min(W, total)
+    edges = [total * w // W for w in range(W + 1)]
+    jobs = [(name, edges[w], edges[w + 1], target_s) for w in range(W)]
+    with mp.get_context("fork").Pool(W) as pool:
+        res = pool.map(_oracle_shard, jobs)
+    units = sum(r[0] for r in res)
+    dt = max(r[1] for r in res)
+    steps = min(r[2] for r in res)
+    return {"value": units / dt, "unit": "robot*step*samples/s", "cores": W, "kind": "oracle",
+            "sample": f"{steps}+ denoising steps of {name} on samples 0..{total - 1}, split over {W} "
+                      f"single-threaded worker processes (sampling, FP64 rollout, reward, weighted update), "
+                      f"{dt:.1f} s"}
 
 
 # the kernels and the host rule that picks their launch shape
@@ -349,6 +373,12 @@ def main():
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
+    cpu = None
+    if not args.experiment and not args.kernel_only and not args.no_cpu_baseline:
+        # the oracle's worker processes are forked before this process
+        # touches the GPU (torch and the HIP library are not loaded yet)
+        cpu = cpu_baseline(args.workload, args.cpu_seconds)
+
     import torch
     from paper_2503_12204_amd import _lib as L
     from paper_2503_12204_amd import workloads as W
@@ -504,8 +534,8 @@ def main():
         "last_iteration": {"reward": st["reward"], "hits": st["hits"], "success": st["success"],
                            "at_goal": st["at_goal"]},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
