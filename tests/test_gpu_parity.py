@@ -392,6 +392,54 @@ def test_cooperative_kernel_is_bit_identical(L, dyn, n, T, M, S, Tb):
         assert np.array_equal(plans[0], pl)
 
 
+@pytest.mark.parametrize("dyn,n,T,S,Tb,n_obs", [
+    (W.HOLO2D, 4, 45, 16, 8, 0),      # pipelined (n S = 64), ragged last block
+    (W.DIFFDRIVE, 8, 100, 8, 20, 0),  # pipelined, the c2 shape with the second heading model
+    (W.UNICYCLE, 8, 33, 8, 34, 0),    # pipelined with a single time block
+    (W.HOLO2D, 8, 50, 8, 12, 3),      # pipelined with obstacles (goal and obstacle terms on replica 1)
+    (W.HOLO3D, 8, 41, 8, 12, 2),      # pipelined 3D with obstacles, ragged
+    (W.UNICYCLE, 5, 47, 8, 10, 2),    # sequential (n S = 40) with obstacles
+    (W.HOLO3D, 16, 30, 8, 8, 0),      # pipelined over two waves of replica 0 (n S = 128)
+])
+def test_cooperative_schedules_match_one_lane_kernel(L, dyn, n, T, S, Tb, n_obs):
+    """Both schedules of the cooperative kernel (pipelined when replica 0 fills
+    whole waves, sequential otherwise), for R = 2 (one replica does the
+    draws, pairs, goal terms and masks), R = 3 (scorer and one worker) and up
+    to 16, with one or several time blocks, a ragged last block and
+    obstacles: draws, rewards, hit counts and a whole iteration equal the
+    one-lane kernel's bit for bit."""
+    from paper_2503_12204_amd import autotune as AT
+    rng = np.random.default_rng(7 * n + T + n_obs)
+    obs = tuple((rng.uniform(-1.0, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(-0.5, 0.5), 0.25) for _ in range(n_obs))
+    M = 96
+    p, x0, g = W.random_instance(rng, dyn, n, T, M, box=max(3.0, n ** 0.5 * 1.5), min_sep=0.6, obstacles=obs)
+    p = p.replace(n_steps=5)
+    ub = _cu(_rand_controls(rng, p, 1, spread=0.5)[0].reshape(-1))
+    du = _cu((rng.normal(size=p.D) * 0.3).astype(np.float32))
+    runs = {}
+    try:
+        for R in (1, 2, 3, 4, 16):
+            if R * S * n > 1024:
+                continue
+            print("cooperative schedule case", W.DYN_NAMES[dyn], n, T, S, Tb, R, n_obs, flush=True)
+            AT.set_tile(p.dyn, n, T, S, Tb, R)
+            step = [_np(t) for t in L.sample_rollout_fitness(p, _cu(x0), _cu(g), ub, du, 2, 4)]
+            ctx = L.Context(p)
+            u = torch.zeros((n, T, p.du), dtype=torch.float32, device="cuda")
+            st = ctx.denoise_iter(_cu(x0), _cu(g), u, 0)
+            ctx.close()
+            runs[R] = (step, _np(u), st)
+    finally:
+        AT.clear_tile(p.dyn, n, T)
+    assert 1 in runs and len(runs) >= 3
+    ref_step, ref_u, ref_st = runs[1]
+    for R, (step, u, st) in runs.items():
+        for a, b in zip(ref_step, step):
+            assert np.array_equal(a, b), f"R = {R}"
+        assert np.array_equal(u, ref_u), f"R = {R}"
+        assert st == ref_st, f"R = {R}"
+
+
 def test_negative_rewards_in_partial_waves(L):
     """A packed 3-robot team (collision penalties make rewards negative) with
     workgroups smaller than a wave: the split calls reproduce the graph
