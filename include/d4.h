@@ -126,9 +126,19 @@ const char* d4_last_error(void);
  *                       and update tiles, but that form is switched off in this
  *                       build (it did not finish on the GPU): setting 1 returns
  *                       D4_EUNSUPPORTED.
+ *  D4_OPT_GEMM_TILE     0 (default): d4p_gemm_bf16 and the proposal's products
+ *                       use 128x128 workgroup tiles when those still give at
+ *                       least 256 workgroups, else 64x64; 64 or 128 fixes the
+ *                       tile.
  * d4_set_option returns D4_EINVAL for an unknown option or a value outside the
  * ranges above; d4_get_option writes the current value to *value (host). */
-enum { D4_OPT_GRAPHS = 0, D4_OPT_ALIGNED_DRAWS = 1, D4_OPT_UPDATE_GRID = 2, D4_OPT_BATCH_PERSISTENT = 3 };
+enum {
+    D4_OPT_GRAPHS = 0,
+    D4_OPT_ALIGNED_DRAWS = 1,
+    D4_OPT_UPDATE_GRID = 2,
+    D4_OPT_BATCH_PERSISTENT = 3,
+    D4_OPT_GEMM_TILE = 4
+};
 int32_t d4_set_option(int32_t option, int32_t value);
 int32_t d4_get_option(int32_t option, int32_t* value);
 

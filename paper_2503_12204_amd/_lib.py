@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libd4.so")
 
 D4_OK, D4_EINVAL, D4_ENOMEM, D4_EHIP, D4_ENONFINITE, D4_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MAX_OBSTACLES = 16
-OPTIONS = {"graphs": 0, "aligned_draws": 1, "update_grid": 2, "batch_persistent": 3}
+OPTIONS = {"graphs": 0, "aligned_draws": 1, "update_grid": 2, "batch_persistent": 3, "gemm_tile": 4}
 
 
 class D4Error(RuntimeError):

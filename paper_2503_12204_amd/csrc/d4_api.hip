@@ -337,6 +337,11 @@ int32_t d4_set_option(int32_t option, int32_t value) {
             if (value == 1) return fail(D4_EUNSUPPORTED, "the persistent batched step is switched off in this build");
             g_opt_batch_persistent.store(value);
             return D4_OK;
+        case D4_OPT_GEMM_TILE:
+            if (value != 0 && value != 64 && value != 128)
+                return fail(D4_EINVAL, "D4_OPT_GEMM_TILE takes 0, 64 or 128, not %d", value);
+            g_opt_gemm_tile.store(value);
+            return D4_OK;
         default: return fail(D4_EINVAL, "unknown option %d", option);
     }
 }
@@ -348,6 +353,7 @@ int32_t d4_get_option(int32_t option, int32_t* value) {
         case D4_OPT_ALIGNED_DRAWS: *value = g_opt_aligned_draws.load(); return D4_OK;
         case D4_OPT_UPDATE_GRID: *value = g_opt_update_grid.load(); return D4_OK;
         case D4_OPT_BATCH_PERSISTENT: *value = g_opt_batch_persistent.load(); return D4_OK;
+        case D4_OPT_GEMM_TILE: *value = g_opt_gemm_tile.load(); return D4_OK;
         default: return fail(D4_EINVAL, "unknown option %d", option);
     }
 }

@@ -31,6 +31,7 @@ inline std::atomic<int> g_opt_graphs{1};
 inline std::atomic<int> g_opt_aligned_draws{1};
 inline std::atomic<int> g_opt_update_grid{0};
 inline std::atomic<int> g_opt_batch_persistent{0};
+inline std::atomic<int> g_opt_gemm_tile{0};
 
 inline int fail(int code, const char* fmt, ...) {
     char buf[512];

@@ -28,12 +28,23 @@ namespace {
 
 inline unsigned blocks(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// 128x128 tiles when they still give at least 256 workgroups (one per CU),
+// else 64x64; D4_OPT_GEMM_TILE fixes either (the results are the same bits)
 template <bool TA, bool TB>
 int gemm(const bf16_t* A, const bf16_t* B, float* C, int M, int N, int K, int lda, int ldb, int ldc, float beta,
          hipStream_t st) {
     if (M <= 0 || N <= 0) return D4_OK;
-    const dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-    hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb, ldc, 1.0f, beta);
+    int tile = g_opt_gemm_tile.load();
+    if (tile == 0) tile = (long long)((M + 127) / 128) * ((N + 127) / 128) >= 256 ? 128 : 64;
+    if (tile == 128) {
+        const dim3 grid((N + 127) / 128, (M + 127) / 128);
+        hipLaunchKernelGGL((k_gemm_bf16<TA, TB, 2, 2>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb, ldc,
+                           1.0f, beta);
+    } else {
+        const dim3 grid((N + 63) / 64, (M + 63) / 64);
+        hipLaunchKernelGGL((k_gemm_bf16<TA, TB, 1, 1>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb, ldc,
+                           1.0f, beta);
+    }
     HIP_LAUNCH_CHECK("k_gemm_bf16");
     return D4_OK;
 }

@@ -1,10 +1,10 @@
 // Kernels of the learned proposal: a permutation-equivariant set network over
 // the robots of each instance, trained on plans the planner solved.
 //
-//  k_gemm_bf16<TA,TB>  C = alpha op(A) op(B) + beta C with BF16 operands and FP32
-//                      accumulation on the 32x32x16 MFMA; op(X) = X or X^T.
-//                      64x64 workgroup tiles, four waves of 32x32, K steps of 32
-//                      staged in LDS k-contiguous for both operands.
+//  k_gemm_bf16<TA,TB,WM,WN>  C = alpha op(A) op(B) + beta C with BF16 operands
+//                      and FP32 accumulation on the 32x32x16 MFMA; op(X) = X or
+//                      X^T.  64x64 or 128x128 workgroup tiles, four waves, K
+//                      steps of 32 staged in LDS k-contiguous for both operands.
 //  elementwise         embedding, bias + ReLU, instance mean / sum pooling and
 //                      their broadcasts, residual sums, masked MSE, column sums,
 //                      Adam with FP32 master weights, BF16 rounding.
@@ -27,7 +27,7 @@ __device__ __forceinline__ bf16_t to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-constexpr int BM = 64, BN = 64, BK = 32, KPAD = 8;
+constexpr int BK = 32, KPAD = 8;
 
 // Eight consecutive BF16 values of one operand row (op = X) or of one stored
 // row of a transposed operand, starting at (outer, inner0): one 16-byte
@@ -52,79 +52,120 @@ __device__ __forceinline__ u32x4 load8_bf16(const bf16_t* __restrict__ X, int ld
     return v;
 }
 
-// C = alpha op(A) op(B) + beta C.  64x64 workgroup tiles, four waves of 32x32
-// on v_mfma_f32_32x32x16_bf16, K in steps of 32.  Each lane moves one group of
-// eight BF16 values per operand and K step with a 16-byte global load (both
-// operands are stored k-contiguous in LDS, so a transposed operand's group is
-// scattered into its eight k rows on the way in).  The LDS tiles are double
-// buffered: the loads of step k+1 go out before the MFMAs of step k, and one
-// barrier per step separates the writes of one buffer from the reads of the
-// other.
-template <bool TA, bool TB>
+// C = alpha op(A) op(B) + beta C.  Workgroup tiles of (64 WM) x (64 WN), four
+// waves in a 2 x 2 grid, each wave WM x WN blocks of 32x32 on
+// v_mfma_f32_32x32x16_bf16, K in steps of 32: 64x64 tiles (WM = WN = 1) for the
+// network's small products, 128x128 (WM = WN = 2) for large ones, where each
+// operand element staged in LDS feeds twice as many MFMAs.  Each lane moves
+// WM (A) and WN (B) groups of eight BF16 values per K step with 16-byte global
+// loads (both operands are stored k-contiguous in LDS, so a transposed
+// operand's group is scattered into its eight k rows on the way in).  The LDS
+// tiles are double buffered: the loads of step k+1 go out before the MFMAs of
+// step k, and one barrier per step separates the writes of one buffer from
+// the reads of the other.  Every output element accumulates its K range in
+// the same order (K steps in turn, 16 k per MFMA) whatever the tile, so both
+// tiles give the same bits.
+template <bool TA, bool TB, int WM, int WN>
 __global__ void __launch_bounds__(256) k_gemm_bf16(const bf16_t* __restrict__ A, const bf16_t* __restrict__ B,
                                                    float* __restrict__ C, int M, int N, int K, int lda,
                                                    int ldb, int ldc, float alpha, float beta) {
-    __shared__ __attribute__((aligned(16))) bf16_t As[2][BM][BK + KPAD];
-    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN][BK + KPAD];
+    constexpr int TM = 64 * WM, TN = 64 * WN;
+    __shared__ __attribute__((aligned(16))) bf16_t As[2][TM][BK + KPAD];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][TN][BK + KPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    // this lane's group: non-transposed, row tid/4 and k (tid%4)*8; transposed, k row tid/8 and
-    // outer (tid%8)*8
-    const int ra = tid >> 2, ka = (tid & 3) * 8;
-    const int kt = tid >> 3, ot = (tid & 7) * 8;
-    auto load_a = [&](int k0) {
-        return TA ? load8_bf16(A, lda, k0 + kt, K, m0 + ot, M) : load8_bf16(A, lda, m0 + ra, M, k0 + ka, K);
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    // group q = tid + 256 g of an operand tile: non-transposed, row q/4 and k
+    // (q%4)*8; transposed (stored [K][outer]), k row q%32 and outer (q/32)*8,
+    // so that the 32 lanes writing one step of the scatter below fill 32
+    // consecutive k of the same LDS row (two to a bank) instead of one k of
+    // rows eight apart (which fall into two banks)
+    auto load_a = [&](int k0, int g) {
+        const int q = tid + 256 * g;
+        return TA ? load8_bf16(A, lda, k0 + (q & 31), K, m0 + (q >> 5) * 8, M)
+                  : load8_bf16(A, lda, m0 + (q >> 2), M, k0 + (q & 3) * 8, K);
     };
-    auto load_b = [&](int k0) {
-        return TB ? load8_bf16(B, ldb, n0 + ra, N, k0 + ka, K) : load8_bf16(B, ldb, k0 + kt, K, n0 + ot, N);
+    auto load_b = [&](int k0, int g) {
+        const int q = tid + 256 * g;
+        return TB ? load8_bf16(B, ldb, n0 + (q >> 2), N, k0 + (q & 3) * 8, K)
+                  : load8_bf16(B, ldb, k0 + (q & 31), K, n0 + (q >> 5) * 8, N);
     };
-    auto store = [&](bf16_t (*T)[BK + KPAD], bool trans, u32x4 v) {
+    auto store = [&](bf16_t (*T)[BK + KPAD], bool trans, int g, u32x4 v) {
+        const int q = tid + 256 * g;
         if (!trans) {
-            *reinterpret_cast<u32x4*>(&T[ra][ka]) = v;
+            *reinterpret_cast<u32x4*>(&T[q >> 2][(q & 3) * 8]) = v;
         } else {
+            const int kr = q & 31, o = (q >> 5) * 8;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) T[ot + i][kt] = (bf16_t)(v[i >> 1] >> (16 * (i & 1)));
+            for (int i = 0; i < 8; ++i) T[o + i][kr] = (bf16_t)(v[i >> 1] >> (16 * (i & 1)));
         }
     };
-    f32x16 acc;
+    f32x16 acc[WM][WN];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    u32x4 va = load_a(0), vb = load_b(0);
-    store(As[0], TA, va);
-    store(Bs[0], !TB, vb);
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    u32x4 va[WM], vb[WN];
+#pragma unroll
+    for (int g = 0; g < WM; ++g) va[g] = load_a(0, g);
+#pragma unroll
+    for (int g = 0; g < WN; ++g) vb[g] = load_b(0, g);
+#pragma unroll
+    for (int g = 0; g < WM; ++g) store(As[0], TA, g, va[g]);
+#pragma unroll
+    for (int g = 0; g < WN; ++g) store(Bs[0], !TB, g, vb[g]);
     __syncthreads();
     int buf = 0;
     for (int k0 = 0; k0 < K; k0 += BK) {
         const bool more = k0 + BK < K;
         if (more) {
-            va = load_a(k0 + BK);
-            vb = load_b(k0 + BK);
+#pragma unroll
+            for (int g = 0; g < WM; ++g) va[g] = load_a(k0 + BK, g);
+#pragma unroll
+            for (int g = 0; g < WN; ++g) vb[g] = load_b(k0 + BK, g);
         }
 #pragma unroll
         for (int kb = 0; kb < BK; kb += 16) {
             const int r = lane & 31, kq = kb + (lane >> 5) * 8;
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 32 + r][kq]);
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 32 + r][kq]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            bf16x8 a[WM], b[WN];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 32 * WM + i * 32 + r][kq]);
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 32 * WN + j * 32 + r][kq]);
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (more) {
-            store(As[buf ^ 1], TA, va);
-            store(Bs[buf ^ 1], !TB, vb);
+#pragma unroll
+            for (int g = 0; g < WM; ++g) store(As[buf ^ 1], TA, g, va[g]);
+#pragma unroll
+            for (int g = 0; g < WN; ++g) store(Bs[buf ^ 1], !TB, g, vb[g]);
         }
         __syncthreads();
         buf ^= 1;
     }
-    // lane l holds column l%32, rows 8*(v/4) + 4*(l/32) + v%4 of the wave's 32x32 block
-    const int col = n0 + wn * 32 + (lane & 31);
+    // lane l holds column l%32, rows 8*(v/4) + 4*(l/32) + v%4 of each 32x32 block
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int row = m0 + wm * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        if (row < M && col < N) {
-            float* c = C + (size_t)row * ldc + col;
-            *c = beta == 0.0f ? alpha * acc[v] : alpha * acc[v] + beta * *c;
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const int col = n0 + wn * 32 * WN + j * 32 + (lane & 31);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = m0 + wm * 32 * WM + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+                if (row < M && col < N) {
+                    float* c = C + (size_t)row * ldc + col;
+                    *c = beta == 0.0f ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * *c;
+                }
+            }
         }
-    }
 }
 
 __global__ void k_cast_bf16(const float* __restrict__ x, bf16_t* __restrict__ y, long long n) {

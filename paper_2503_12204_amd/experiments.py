@@ -423,6 +423,7 @@ def gemm_roofline(L, rows=640, width=256, hidden=512, d_out=200, batch=64, large
         ("weight gradient: [R x W]^T [R x H]", width, hidden, rows, True, False),
         ("input gradient: [R x H] [W x H]^T", rows, width, hidden, False, True),
         (f"large square {large}", large, large, large, False, False),
+        (f"large square {large}, B transposed", large, large, large, False, True),
     ]
     out = []
     s = torch.cuda.current_stream()

@@ -144,6 +144,11 @@ def test_launch_options_without_a_gpu(L):
     assert lib.d4_set_option(0, 2) == L.D4_EINVAL
     assert lib.d4_set_option(1, -1) == L.D4_EINVAL
     assert lib.d4_set_option(2, -5) == L.D4_EINVAL
+    assert L.get_option("gemm_tile") == 0
+    with L.option("gemm_tile", 128):
+        assert L.get_option("gemm_tile") == 128
+    assert L.get_option("gemm_tile") == 0
+    assert lib.d4_set_option(4, 96) == L.D4_EINVAL
     assert lib.d4_set_option(9, 0) == L.D4_EINVAL
     assert lib.d4_get_option(9, ctypes.byref(v)) == L.D4_EINVAL
     assert lib.d4_get_option(0, None) == L.D4_EINVAL

@@ -48,6 +48,31 @@ def test_gemm_forms(L, ta, tb, M, N, K):
     assert np.abs(C2.cpu().numpy() - (ref + 1.0)).max() <= tol
 
 
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("M,N,K", [(2048, 2048, 96), (300, 200, 72), (129, 257, 8)])
+def test_gemm_tiles_give_the_same_bits(L, ta, tb, M, N, K):
+    """The 128x128 and 64x64 workgroup tiles accumulate every output element
+    in the same order, so they give the same bits, ragged edges included
+    (2048 x 2048 is where the default picks 128x128); the 128x128 result also
+    meets the FP64 reference's bar."""
+    rng = np.random.default_rng(M + N + K)
+    A = rng.normal(size=(K, M) if ta else (M, K)).astype(np.float32)
+    B = rng.normal(size=(N, K) if tb else (K, N)).astype(np.float32)
+    Ab, Bb = _bf16(A).cuda(), _bf16(B).cuda()
+    out = {}
+    for tile in (64, 128):
+        with L.option("gemm_tile", tile):
+            out[tile] = L.gemm_bf16(Ab, Bb, M, N, K, ta, tb).cpu().numpy()
+    assert np.array_equal(out[64], out[128])
+    default = L.gemm_bf16(Ab, Bb, M, N, K, ta, tb).cpu().numpy()
+    assert np.array_equal(default, out[64])
+    a64 = Ab.cpu().float().numpy().astype(np.float64)
+    b64 = Bb.cpu().float().numpy().astype(np.float64)
+    ref = (a64.T if ta else a64) @ (b64.T if tb else b64)
+    tol = 1e-5 * np.sqrt(K) * (np.abs(a64).max() * np.abs(b64).max() * np.sqrt(K)) + 1e-6
+    assert np.abs(out[128] - ref).max() <= tol
+
+
 def _problem(rng, R_per, d_in, d_out):
     seg = np.concatenate([[0], np.cumsum(R_per)]).astype(np.int32)
     R = int(seg[-1])
