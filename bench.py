@@ -342,6 +342,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="holo3d_sphere_swap", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose the workload's tile with d4_autotune (whole iterations) before timing")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="only launch the fused kernel this many times (for counter runs)")
@@ -475,6 +477,9 @@ def main():
         print("copy calibration: 256 MiB read + 256 MiB write", flush=True)
         return
 
+    if args.tune:
+        from paper_2503_12204_amd import autotune as AT
+        AT.tune(p, x0n, gn, force=True)
     u = torch.zeros((p.n_robots, p.horizon, p.du), dtype=torch.float32, device="cuda")
     ctx = L.Context(p)
     for k in range(args.warmup):

@@ -274,16 +274,28 @@ int32_t d4_batch_tile_set(int32_t dyn, int32_t n_lo, int32_t n_hi, int32_t t_lo,
 int32_t d4_tile_get(const d4_problem* p, int32_t batched, int32_t* samples_per_group, int32_t* steps_per_block,
                     int32_t* replicas);
 
-/* Time every admissible tile on the current device with the fused kernel of
- * problem p on the start states x0 [n][d_x] and goals goal [n][d_p] (device
- * arrays; the broad phase of the pair checks makes the cost depend on where
- * the robots are), with zero controls.  Scratch buffers are allocated and
- * freed here; synchronises the null stream.  Installs the fastest tile and
- * reports it (outputs are host pointers, each may be NULL).  The library
- * keeps installed tiles in memory only: the persistent cache of tuned tiles
- * (keyed by architecture, kernel source version and problem shape) is the
- * Python layer's (paper_2503_12204_amd/autotune.py), which reinstalls them
- * with d4_tile_set, so this call takes no cache path. */
+/* Choose the launch tile of problem p on the current device by timing whole
+ * iterations (Algorithm 2's loop body: N denoising steps and the apply step).
+ * One iteration from zero controls under the rule gives a representative
+ * plan; the iteration from that plan is then timed (one untimed run, the
+ * least of reps, reps < 1 meaning 2) with the rule's tile and with each
+ * candidate around it: samples per group S/2, S and 2S of the rule's S,
+ * 1..16 replica lanes and 4..64 steps per block, when admissible.  x0 [n][d_x]
+ * and goal [n][d_p] are device arrays: the broad phase of the pair checks
+ * makes the cost depend on where the robots are.  A tile other than the
+ * rule's is installed (as by d4_tile_set) only when it is at least 1 % faster;
+ * otherwise the rule stays and any tile installed for this shape is removed.
+ * Reports the chosen tile and its time per denoising step in microseconds
+ * (outputs are host pointers, each may be NULL).  Allocates a context and a
+ * plan buffer, frees them before returning, and synchronises its own stream.
+ * Tiles change speed, never results.  The library keeps installed tiles in
+ * memory only: the persistent cache of tuned tiles (keyed by architecture,
+ * kernel source version and problem shape) is the Python layer's
+ * (paper_2503_12204_amd/autotune.py), which reinstalls them with
+ * d4_tile_set, so this call takes no cache path.  Errors: D4_EINVAL for a bad
+ * problem or NULL inputs, D4_EUNSUPPORTED above 16384 samples, D4_ENOMEM or
+ * D4_EHIP when its buffers or timings fail (any tile installed before the
+ * call is then left as it was). */
 int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int32_t reps,
                     int32_t* samples_per_group, int32_t* steps_per_block, int32_t* replicas, float* best_us);
 

@@ -69,9 +69,12 @@ def get_tile(p, batched=False):
     return S.value, Tb.value, R.value
 
 
-def tune(p, x0, goal, path=DEFAULT_CACHE, reps=5, force=False):
-    """Tile for problem p: from the cache, else measured now on the start
-    states x0 [n][d_x] and goals [n][d_p] (and cached).  The cost of the pair
+def tune(p, x0, goal, path=DEFAULT_CACHE, reps=2, force=False):
+    """Tile for problem p: from the cache, else measured now by d4_autotune
+    on the start states x0 [n][d_x] and goals [n][d_p] (and cached).
+    d4_autotune times whole iterations from a plan one iteration old and keeps
+    the rule's tile unless a candidate is at least 1 % faster; the entry's
+    "us" is the chosen tile's time per denoising step.  The cost of the pair
     checks depends on how close the robots come, so tune on a representative
     instance of the shape."""
     cache = _load(path)

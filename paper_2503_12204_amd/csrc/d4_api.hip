@@ -767,75 +767,108 @@ int32_t d4_autotune(const d4_problem* p, const float* x0, const float* goal, int
     if (rc) return rc;
     NEED(x0);
     NEED(goal);
-    if (reps < 1) reps = 5;
+    if (reps < 1) reps = 2;
+    if (p->n_samples > 16384)
+        return fail(D4_EUNSUPPORTED, "n_samples %d above the 16384 weights one workgroup stages", p->n_samples);
     const Shape s = shape_of(p->dyn);
-    const size_t n = p->n_robots, T = p->horizon, M = p->n_samples, D = n * T * s.du;
-    float *eps = nullptr, *r = nullptr, *ub = nullptr;
-    int* hits = nullptr;
+    const int n = p->n_robots, cs = s.du == 2 ? 2 : 4;
+    const size_t D = (size_t)n * p->horizon * s.du;
+    d4_ctx* c = nullptr;
+    rc = d4_ctx_create(p, &c);
+    if (rc) return rc;
+    float* u1 = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    Tile prev;
+    const bool had_prev = tile_override(p->dyn, n, p->horizon, &prev);
+    auto set_override = [&](const Tile* t) {
+        std::lock_guard<std::mutex> lk(g_tile_mu);
+        const auto key = std::make_tuple((int)p->dyn, n, (int)p->horizon);
+        if (t) g_tiles[key] = *t;
+        else g_tiles.erase(key);
+    };
     auto release = [&]() {
-        for (void* q : {(void*)eps, (void*)r, (void*)ub, (void*)hits})
-            if (q) (void)hipFree(q);
+        if (u1) (void)hipFree(u1);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
+        (void)d4_ctx_destroy(c);
     };
-    if (hipMalloc(&eps, 4 * D * M) != hipSuccess || hipMalloc(&r, 4 * M) != hipSuccess ||
-        hipMalloc(&hits, 4 * M) != hipSuccess || hipMalloc(&ub, 4 * D) != hipSuccess) {
+    auto give_up = [&](int code, const char* what) {
+        set_override(had_prev ? &prev : nullptr);
         release();
-        return fail(D4_ENOMEM, "autotune scratch allocation failed");
-    }
-    (void)hipMemset(ub, 0, 4 * D);
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        release();
-        return fail(D4_EHIP, "autotune could not create its timing events");
-    }
-    const Schedule sc = make_schedule(p);
-    float best = 1e30f;
-    Tile best_t = default_tile(p->dyn, p->n_robots);
-    const int cs = s.du == 2 ? 2 : 4;
-    for (int R : {1, 2, 4, 8, 16}) for (int S : {4, 8, 16, 32, 64}) {
-        for (int Tb : {2, 4, 8, 12, 16, 32}) {
-            Tile t;
-            t.S = S;
-            t.Tb = Tb;
-            t.R = R;
-            if (Tb % cs) continue;
-            if (R > 1 && S * p->n_robots * R < 64) continue;
-            if (tile_ok(p, t)) continue;
-            RollFitArgs a = base_args(p, t);
-            a.x0 = x0;
-            a.goal = goal;
-            a.u_base = ub;
-            a.du_in = ub;
-            a.eps = eps;
-            a.r = r;
-            a.hits = hits;
-            a.step = (uint32_t)p->n_steps;
-            a.mean_scale = sc.ms[p->n_steps];
-            a.sigma = sc.sigma[p->n_steps];
-            rc = launch_rollfit<false>(p, a, t, 0);
-            if (rc) continue;
-            (void)hipEventRecord(e0, 0);
-            for (int k = 0; k < reps; ++k) launch_rollfit<false>(p, a, t, 0);
-            (void)hipEventRecord(e1, 0);
-            if (hipEventSynchronize(e1) != hipSuccess) continue;
+        return fail(code, "autotune: %s", what);
+    };
+    if (hipMalloc(&u1, 4 * D) != hipSuccess) return give_up(D4_ENOMEM, "plan buffer allocation failed");
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return give_up(D4_EHIP, "could not create its timing events");
+    hipStream_t st = c->cap_stream;
+    const IterBuffers b = ctx_buffers(c);
+    const Shape sh = shape_of(p->dyn);
+    if (hipMemcpyAsync(c->x0, x0, 4 * n * sh.dx, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(c->goal, goal, 4 * n * sh.dp, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemsetAsync(c->ubase, 0, 4 * D, st) != hipSuccess)
+        return give_up(D4_EHIP, "could not stage its inputs");
+    // a representative plan: one iteration from zero controls under the rule
+    set_override(nullptr);
+    const Tile rule = pick_tile(p);
+    hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, st, c->iter, 0u, c->status);
+    if (enqueue_iteration(p, b, st) != D4_OK) return give_up(D4_EHIP, "the first iteration failed");
+    if (hipMemcpyAsync(u1, c->ubase, 4 * D, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return give_up(D4_EHIP, "the first iteration failed");
+    // time of the iteration from that plan with tile t installed (the rule when
+    // t is null): one untimed run, then the least of `reps`
+    auto time_tile = [&](const Tile* t) -> float {
+        set_override(t);
+        float best = 1e30f;
+        for (int k = 0; k <= reps; ++k) {
+            if (hipMemcpyAsync(c->ubase, u1, 4 * D, hipMemcpyDeviceToDevice, st) != hipSuccess) return 1e30f;
+            hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, st, c->iter, 1u, c->status);
+            (void)hipEventRecord(e0, st);
+            if (enqueue_iteration(p, b, st) != D4_OK) return 1e30f;
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) return 1e30f;
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            const float us = ms * 1000.0f / reps;
-            if (us < best) {
-                best = us;
-                best_t = t;
+            if (k > 0 && ms < best) best = ms;
+        }
+        return best;
+    };
+    const float t_rule = time_tile(nullptr);
+    if (t_rule >= 1e30f) return give_up(D4_EHIP, "the rule's tile could not be timed");
+    float t_best = t_rule;
+    Tile best_t = rule;
+    for (int S : {rule.S / 2, rule.S, rule.S * 2}) {
+        if (S < 1 || S > 64) continue;
+        for (int R : {1, 2, 4, 8, 16}) {
+            if (R > 1 && S * n * R < 64) continue;  // a cooperative workgroup below one wave
+            for (int Tb : {4, 8, 12, 16, 20, 24, 32, 48, 64}) {
+                Tile t;
+                t.S = S;
+                t.Tb = Tb;
+                t.R = R;
+                if (Tb % cs || (t.S == rule.S && t.Tb == rule.Tb && t.R == rule.R)) continue;
+                if (S * n > 256 || R * S * n > 1024 || rollfit_lds(p, t) > LDS_DYNAMIC_MAX) continue;
+                const float tm = time_tile(&t);
+                if (tm < t_best) {
+                    t_best = tm;
+                    best_t = t;
+                }
             }
         }
     }
+    // a tile other than the rule's is kept only when it is at least 1 % faster
+    if (t_best > 0.99f * t_rule) {
+        best_t = rule;
+        t_best = t_rule;
+        set_override(nullptr);
+    } else {
+        set_override(&best_t);
+    }
     release();
-    if (best >= 1e30f) return fail(D4_EHIP, "no tile could be timed");
-    rc = d4_tile_set(p->dyn, p->n_robots, p->horizon, best_t.S, best_t.Tb, best_t.R);
-    if (rc) return rc;
     if (samples_per_group) *samples_per_group = best_t.S;
     if (steps_per_block) *steps_per_block = best_t.Tb;
     if (replicas) *replicas = best_t.R;
-    if (best_us) *best_us = best;
+    if (best_us) *best_us = t_best * 1000.0f / (float)p->n_steps;
     return D4_OK;
 }
 
