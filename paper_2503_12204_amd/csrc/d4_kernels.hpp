@@ -309,6 +309,11 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
 
     const int nblk = (T + Tb - 1) / Tb;
     for (int b = 0; b < nblk; ++b) {
+        // The draw-and-rollout loop runs at raised wave priority, the pair
+        // phases at the default: when the two waves sharing a SIMD are in
+        // different phases, the VALU-dense one issues first (c3 iterations
+        // 3 % faster than with equal priorities; the results do not change).
+        __builtin_amdgcn_s_setprio(2);
         const int buf = b & 1;
         const int t0 = b * Tb;
         const int tcount = min(Tb, T - t0);
@@ -389,6 +394,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
             for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
             anyhit[buf * S + ms] = 0u;
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         // broad phase: partners whose block boxes come within the threshold
         uint32_t near = 0u;
