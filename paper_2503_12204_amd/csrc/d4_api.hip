@@ -105,7 +105,8 @@ int launch_update(const d4_problem* p, const float* eps, const float* r, const f
     // register form when the rows are whole float4s; LDS form otherwise
     const int J = upd_reg_j(M, eps, r);
     if (J > 0) {
-        int grid = std::max(1, std::min(512, (D + UPD_ROWS - 1) / UPD_ROWS));
+        // at most 512 workgroups, of two rows each when D is small
+        int grid = std::max(1, std::min(512, (D + 1) / 2));
         if (const int g = g_opt_update_grid.load()) grid = std::max(1, std::min(D, g));
         switch (J) {
             case 1: hipLaunchKernelGGL(k_softmax_update_reg<1>, dim3(grid), dim3(256), 0, st, a); break;

@@ -180,7 +180,7 @@ struct Chunk {
 // Chunk::STEPS.  MODE_FROM_X reads trajectories instead.
 // One tile: samples m0 .. m0+S-1 of one problem, lanes tid < n*S (the rest of
 // the workgroup idles through the barriers).
-template <int DYN, int MODE, int NS = NARROW_STEPS>
+template <int DYN, int MODE, int NS = NARROW_STEPS, bool PRIO = true>
 __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float* lds) {
     using DY = Dyn<DYN>;
     constexpr int DX = DY::DX, DU = DY::DU, DP = DY::DP;
@@ -313,7 +313,9 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
         // phases at the default: when the two waves sharing a SIMD are in
         // different phases, the VALU-dense one issues first (c3 iterations
         // 3 % faster than with equal priorities; the results do not change).
-        __builtin_amdgcn_s_setprio(2);
+        // The batched kernel, whose neighbouring tiles belong to different
+        // instances, runs 1 % faster without it (PRIO = false).
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
         const int buf = b & 1;
         const int t0 = b * Tb;
         const int tcount = min(Tb, T - t0);
@@ -394,7 +396,7 @@ __device__ __forceinline__ void rollfit_tile(const RollFitArgs& a, int m0, float
             for (int tt = 0; tt < tcount; ++tt) mask[(buf * Tb + tt) * S + ms] = 0u;
             anyhit[buf * S + ms] = 0u;
         }
-        __builtin_amdgcn_s_setprio(0);
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         // broad phase: partners whose block boxes come within the threshold
         uint32_t near = 0u;
@@ -1031,14 +1033,16 @@ __device__ __forceinline__ f4v load4_checked(__amdgpu_buffer_rsrc_t rs, int byte
 // The same update for a sample count that is a multiple of 4, with the
 // weights in registers: lane t of the 256-lane workgroup owns the float4
 // columns t + 256 j (j < J, J * 1024 >= M) of the rewards, the weights and of
-// every eps row.  The workgroup handles rows e0 .. e1-1, UPD_ROWS at a time;
-// the first rows' loads are issued before the statistics so that their
-// latency overlaps the softmax.  Loads are range-checked buffer loads (columns
+// every eps row.  The workgroup handles rows e0 .. e1-1, upd_rows(J) at a
+// time (more rows per pass when a lane owns fewer columns, so that each pass
+// keeps 8-32 KiB of loads in flight per workgroup); the first rows' loads are
+// issued before the statistics so that their latency overlaps the softmax.  Loads are range-checked buffer loads (columns
 // past M read as zero and carry weight zero), so no load needs a guard.
 // Statistics are taken per lane over its columns in j order, then across the
 // wave and the workgroup in a fixed order: every workgroup (of this launch
 // and of the batched form) computes the same weights bit for bit.
-constexpr int UPD_ROWS = 2;
+constexpr int UPD_ROWS_MAX = 8;
+constexpr int upd_rows(int J) { return J >= 4 ? 2 : J == 2 ? 4 : 8; }
 
 __device__ __forceinline__ float block_sum4(float s, float* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1061,7 +1065,8 @@ template <int J, int AUX = 0>
 __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0, int e1, bool first) {
 #pragma clang fp contract(off)
     __shared__ float red[4];
-    __shared__ float rowred[UPD_ROWS][4];
+    constexpr int UPD_ROWS = upd_rows(J);
+    __shared__ float rowred[UPD_ROWS_MAX][4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int M = a.M, M4 = M >> 2;
     const __amdgpu_buffer_rsrc_t r_rs =
@@ -1070,14 +1075,20 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
 #pragma unroll
     for (int j = 0; j < J; ++j) w[j] = load4_checked<AUX>(r_rs, (tid + 256 * j) * 16);
     f4v x[UPD_ROWS][J];
+    // rows past e1 (the last pass of a short range) are not loaded; their
+    // sums are formed from zeros and not written
     auto load_rows = [&](int e) {
 #pragma unroll
         for (int q = 0; q < UPD_ROWS; ++q) {
-            const int ee = min(e + q, e1 - 1);
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float*>(a.eps + (size_t)ee * M), (short)0, M * 4, 0x00020000);
+            if (e + q < e1) {
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<float*>(a.eps + (size_t)(e + q) * M), (short)0, M * 4, 0x00020000);
 #pragma unroll
-            for (int j = 0; j < J; ++j) x[q][j] = load4_checked<AUX>(rs, (tid + 256 * j) * 16);
+                for (int j = 0; j < J; ++j) x[q][j] = load4_checked<AUX>(rs, (tid + 256 * j) * 16);
+            } else {
+#pragma unroll
+                for (int j = 0; j < J; ++j) x[q][j] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+            }
         }
     };
     if (e0 < e1) load_rows(e0);
@@ -1400,20 +1411,20 @@ __device__ __forceinline__ void batch_reward_tile(const BatchStepArgs& b, int in
     const bool al = in.mode == MODE_FUSED_ALIGNED;
     switch (in.dyn) {
         case HOLO2D:
-            if (al) rollfit_tile<HOLO2D, MODE_FUSED_ALIGNED, 1>(a, tl.m0, lds);
-            else rollfit_tile<HOLO2D, MODE_FUSED, 1>(a, tl.m0, lds);
+            if (al) rollfit_tile<HOLO2D, MODE_FUSED_ALIGNED, 1, false>(a, tl.m0, lds);
+            else rollfit_tile<HOLO2D, MODE_FUSED, 1, false>(a, tl.m0, lds);
             break;
         case HOLO3D:
-            if (al) rollfit_tile<HOLO3D, MODE_FUSED_ALIGNED, 1>(a, tl.m0, lds);
-            else rollfit_tile<HOLO3D, MODE_FUSED, 1>(a, tl.m0, lds);
+            if (al) rollfit_tile<HOLO3D, MODE_FUSED_ALIGNED, 1, false>(a, tl.m0, lds);
+            else rollfit_tile<HOLO3D, MODE_FUSED, 1, false>(a, tl.m0, lds);
             break;
         case UNICYCLE:
-            if (al) rollfit_tile<UNICYCLE, MODE_FUSED_ALIGNED, 1>(a, tl.m0, lds);
-            else rollfit_tile<UNICYCLE, MODE_FUSED, 1>(a, tl.m0, lds);
+            if (al) rollfit_tile<UNICYCLE, MODE_FUSED_ALIGNED, 1, false>(a, tl.m0, lds);
+            else rollfit_tile<UNICYCLE, MODE_FUSED, 1, false>(a, tl.m0, lds);
             break;
         default:
-            if (al) rollfit_tile<DIFFDRIVE, MODE_FUSED_ALIGNED, 1>(a, tl.m0, lds);
-            else rollfit_tile<DIFFDRIVE, MODE_FUSED, 1>(a, tl.m0, lds);
+            if (al) rollfit_tile<DIFFDRIVE, MODE_FUSED_ALIGNED, 1, false>(a, tl.m0, lds);
+            else rollfit_tile<DIFFDRIVE, MODE_FUSED, 1, false>(a, tl.m0, lds);
             break;
     }
 }
