@@ -188,8 +188,13 @@ def cpu_baseline(name, target_s=10.0, workers=None):
     W = min(W, total)
     edges = [total * w // W for w in range(W + 1)]
     jobs = [(name, edges[w], edges[w + 1], target_s) for w in range(W)]
-    with mp.get_context("fork").Pool(W) as pool:
-        res = pool.map(_oracle_shard, jobs)
+    try:
+        with mp.get_context("fork").Pool(W) as pool:
+            res = pool.map(_oracle_shard, jobs)
+    except Exception as exc:  # no worker processes here: one in-process worker
+        print(f"cpu_baseline: worker processes failed ({exc}); timing one core", file=sys.stderr, flush=True)
+        W, total = 1, min(p.n_samples, 1024)
+        res = [_oracle_shard((name, 0, total, target_s))]
     units = sum(r[0] for r in res)
     dt = max(r[1] for r in res)
     steps = min(r[2] for r in res)
