@@ -247,10 +247,13 @@ int32_t d4_denoise_iter_noalloc(const d4_problem* p, const float* x0, const floa
  * workgroup S (1..64), the number of steps per LDS time block (a multiple of
  * 2 for d_u = 2, of 4 for d_u = 3) and the replica lanes R per (sample,
  * robot) (1..16; R > 1 lets R lanes share the draws and pair checks of one
- * lane, for problems with too few lanes to fill the GPU), with
- * S * n_robots <= 256 and R * S * n_robots <= 1024.  A tile changes only
- * speed: every admissible tile gives the same bits.  The batched form keeps
- * its own rule (R = 1).
+ * lane, for problems with too few lanes to fill the GPU; when S * n_robots is
+ * a multiple of 64 the replicas also pipeline the serial rollout of one time
+ * block against the draws of the next and the pair checks of the previous
+ * one), with S * n_robots <= 256 and R * S * n_robots <= 1024.  A tile
+ * changes only speed: every admissible tile gives the same bits.  The
+ * batched form uses its own rule or the bucket tiles of d4_batch_tile_set
+ * (R = 1).
  * ------------------------------------------------------------------------ */
 
 /* Install (or, with samples_per_group = 0, remove) a process-wide tile for
