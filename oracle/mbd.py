@@ -23,9 +23,13 @@ guidance give Eq. mbd-denoising, weights summing to one, uniform weights for
 equal rewards, the temperature identity of the normalisation, and, over all
 N steps, the closed form of a linear fitness (the tilt accumulated through the
 schedule) for the chained update and for the loop of denoise_iteration
-(tests/test_oracle_mbd.py).  The planner with the robot fitness beyond one
-step is "parity unpinned": only the chain of pinned steps and the paper's
-distribution-level outcomes speak for it.
+(tests/test_oracle_mbd.py).  With the robot fitness, one step on two samples
+and the whole loop body (two steps, then the apply step, and plan) are
+pinned by a hand-worked two-robot case whose draws are large enough that the
+control clip fixes every rollout: positions, rewards, pair counts, weights,
+the carried deformation and the final plan are worked out by hand.  Beyond
+such cases the planner's trajectories are the composition of these pinned
+steps.
 """
 import numpy as np
 

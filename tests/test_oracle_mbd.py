@@ -245,3 +245,99 @@ def test_one_sample_step_moves_the_plan_by_its_own_deformation():
     assert np.allclose(out["w"], [1.0])
     assert np.allclose(out["du_next"], os_[i] * du.reshape(-1), rtol=1e-14, atol=1e-15)
     assert np.allclose(out["x"][0, 0], x_expect, rtol=0, atol=1e-14)
+
+
+def _swap_pair_case(n_steps):
+    """Two 2D double integrators 3 m apart on the x axis, each with its goal
+    4 m away past the other robot; T = 2, dt = 1, w_safe = 1, reward distance
+    2 R_a + epsilon = 2.5 m, lambda = 0.5, batch-normalised rewards.  A sample
+    drives both robots either toward their goals at full thrust at t = 0
+    ("toward") or away from them ("away") and coasts at t = 1; its draws are
+    so large that the clip decides the controls whatever sigma_i is.  Worked
+    out by hand (RK4 is exact for the double integrator: p1 = p0 + a/2,
+    v1 = a, p2 = p1 + v1):
+      toward: robot 0 at (0.5, 0), (1.5, 0); robot 1 at (2.5, 0), (1.5, 0);
+              r_goal = 1 - 3.5/4 and 1 - 2.5/4 for each robot; the robots are
+              2 m and 0 m apart, r_safe = -1 for both at both steps, so
+              r = (2 (0.125 + 0.375) - 4) / 4 = -0.75 and hits = 2;
+      away:   robot 0 at (-0.5, 0), (-1.5, 0); robot 1 at (3.5, 0), (4.5, 0);
+              r_goal = 1 - 4.5/4 and 1 - 5.5/4, no pair within 2.5 m, so
+              r = 2 (-0.125 - 0.375) / 4 = -0.25 and hits = 0.
+    The batch z-scores of (-0.75, -0.25) are (-1, +1), so the weights are
+    exp(-4) / (1 + exp(-4)) for "toward" and 1 / (1 + exp(-4)) for "away".
+    Deformation elements run e = k T d_u + t d_u + d (robot, step, axis): the
+    "toward" direction is +1 on element 0 (robot 0, t = 0, a_x) and -1 on
+    element 4 (robot 1, t = 0, a_x)."""
+    p = W.Problem(dyn=W.HOLO2D, n_robots=2, horizon=2, n_samples=2, n_steps=n_steps, dt=1.0,
+                  robot_radius=1.0, safety_margin=0.5, w_safe=1.0, temperature=0.5, v_max=2.0)
+    x0 = np.array([[0.0, 0.0, 0.0, 0.0], [3.0, 0.0, 0.0, 0.0]])
+    goal = np.array([[4.0, 0.0], [-1.0, 0.0]])
+    toward = np.zeros(8)
+    toward[0], toward[4] = 1.0, -1.0
+    w_away = 1.0 / (1.0 + np.exp(-4.0))
+    w_toward = np.exp(-4.0) / (1.0 + np.exp(-4.0))
+    pos = {"toward": [[(0.5, 0.0), (1.5, 0.0)], [(2.5, 0.0), (1.5, 0.0)]],
+           "away": [[(-0.5, 0.0), (-1.5, 0.0)], [(3.5, 0.0), (4.5, 0.0)]]}
+    return p, x0, goal, toward, w_toward, w_away, pos
+
+
+def test_two_sample_step_with_the_robot_fitness():
+    """One denoising step of Algorithm 1 with the robot fitness of Eq.
+    generic-reward on two samples: the rollouts, rewards, pair counts,
+    weights and the update Delta U_{i-1} = sqrt(abar_{i-1}) sum_m w_m sigma_i
+    eps^(m) (Delta U_i = 0) against the hand-worked case above.  A dropped
+    safety term ranks "toward" first; deformation elements in another order,
+    or a sample's rollout scored as another's, move the robots elsewhere."""
+    p, x0, goal, toward, w_toward, w_away, pos = _swap_pair_case(3)
+    ms, sg, os_ = schedule.step_scalars(p.n_steps, p.beta_min, p.beta_max)
+    i, L = 2, 1e3
+    eps = np.stack([L * toward, -L * toward], axis=1)        # [D][M]: sample 0 toward, 1 away
+    out = mbd.denoise_step(p, x0, goal, np.zeros(p.D), np.zeros(p.D), 0, i, eps=eps)
+    for m, key in enumerate(("toward", "away")):
+        for k in range(2):
+            for t in range(2):
+                assert np.allclose(out["x"][m, k, t + 1, :2], pos[key][k][t], rtol=0, atol=1e-15)
+    assert np.allclose(out["r"], [-0.75, -0.25], rtol=0, atol=1e-15)
+    assert list(out["hits"]) == [2, 0] and list(out["robots_hit"]) == [4, 0]
+    assert np.allclose(out["w"], [w_toward, w_away], rtol=1e-14, atol=0)
+    expect = os_[i] * sg[i] * L * (w_toward - w_away) * toward
+    assert np.allclose(out["du_next"], expect, rtol=1e-13, atol=1e-12)
+
+
+def test_planner_iteration_with_the_robot_fitness(monkeypatch):
+    """The oracle's Algorithm 2 loop body (denoise_iteration) and plan with the
+    robot fitness, N = 2, on the hand-worked case above with the draws of each
+    step fixed: step 2 offers (toward, away) and keeps mostly "away", step 1
+    offers (away, toward) with draws a thousand times larger, so that its
+    clip again ignores the carried deformation.  By hand:
+      Delta U_1 = sqrt(abar_1) sigma_2 L (w_t - w_a) v,
+      Delta U_0 = sqrt(abar_0) (Delta U_1 / sqrt(abar_1) + sigma_1 L' (w_t - w_a) v)
+    (the weights sum to one, so the carried part passes through whole), with
+    v the "toward" direction and w_t < w_a; the plan clip(Delta U_0) is the
+    full-thrust "away" control, whose rollout scores -0.25 with no pair
+    within the reward distance.  Steps visited out of order, or one step's
+    update not carried into the next, miss Delta U_0."""
+    p, x0, goal, toward, w_toward, w_away, _ = _swap_pair_case(2)
+    ms, sg, os_ = schedule.step_scalars(p.n_steps, p.beta_min, p.beta_max)
+    L, L1 = 1e3, 1e6
+    draws = {2: np.stack([L * toward, -L * toward], axis=1), 1: np.stack([-L1 * toward, L1 * toward], axis=1)}
+    visited = []
+
+    def fixed_draw(seed, inst, kappa, step, M, D, samples=None):
+        assert (M, D, samples) == (2, 8, None)
+        visited.append(step)
+        return draws[step]
+
+    monkeypatch.setattr(noise, "draw", fixed_draw)
+    res = mbd.denoise_iteration(p, x0, goal, np.zeros(p.D), 0)
+    assert visited == [2, 1]
+    du1 = os_[2] * sg[2] * L * (w_toward - w_away) * toward
+    du0 = os_[1] * (ms[1] * du1 + sg[1] * L1 * (w_toward - w_away) * toward)
+    assert np.allclose(res["du0"], du0, rtol=1e-13, atol=1e-9)
+    away_u = np.zeros((2, 2, 2))
+    away_u[0, 0, 0], away_u[1, 0, 0] = -1.0, 1.0
+    assert np.array_equal(res["u"], away_u)
+    assert abs(res["r"] + 0.25) < 1e-15 and res["hits"] == 0 and res["success"] and not res["at_goal"]
+    visited.clear()
+    u, hist = mbd.plan(p, x0, goal, iterations=1)
+    assert visited == [2, 1] and np.array_equal(u, away_u) and abs(hist[0]["r"] + 0.25) < 1e-15
