@@ -1044,27 +1044,33 @@ __device__ __forceinline__ f4v load4_checked(__amdgpu_buffer_rsrc_t rs, int byte
 constexpr int UPD_ROWS_MAX = 8;
 constexpr int upd_rows(int J) { return J >= 4 ? 2 : J == 2 ? 4 : 8; }
 
+// Workgroup (four waves) sum, and sum with maximum, through LDS slots that
+// no other reduction of the same call reuses, so one barrier each suffices.
 __device__ __forceinline__ float block_sum4(float s, float* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     s = wave_sum(s);
-    __syncthreads();
     if (lane == 0) red[wave] = s;
     __syncthreads();
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
-__device__ __forceinline__ float block_max4(float s, float* red) {
+__device__ __forceinline__ void block_sum_max4(float& s, float& m, float* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    s = wave_max(s);
+    s = wave_sum(s);
+    m = wave_max(m);
+    if (lane == 0) {
+        red[wave] = s;
+        red[4 + wave] = m;
+    }
     __syncthreads();
-    if (lane == 0) red[wave] = s;
-    __syncthreads();
-    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    s = (red[0] + red[1]) + (red[2] + red[3]);
+    m = fmaxf(fmaxf(red[4], red[5]), fmaxf(red[6], red[7]));
 }
 
 template <int J, int AUX = 0>
 __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0, int e1, bool first) {
 #pragma clang fp contract(off)
-    __shared__ float red[4];
+    // statistics slots: sum and maximum [0, 8), squares [8, 12), exponentials [12, 16)
+    __shared__ float red[16];
     constexpr int UPD_ROWS = upd_rows(J);
     __shared__ float rowred[UPD_ROWS_MAX][4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1103,8 +1109,7 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
             mx = fmaxf(fmaxf(mx, fmaxf(w[j].x, w[j].y)), fmaxf(w[j].z, w[j].w));
         }
     }
-    sum = block_sum4(sum, red);
-    mx = block_max4(mx, red);
+    block_sum_max4(sum, mx, red);
     const float mean = sum / (float)M;
     float q = 0.0f;
 #pragma unroll
@@ -1120,7 +1125,7 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
             q = __builtin_fmaf(d, d, q);
         }
     }
-    q = block_sum4(q, red);
+    q = block_sum4(q, red + 8);
     const bool bad = !isfinite(mean) || !isfinite(q) || !isfinite(mx);
     float mu = 0.0f, scale = a.inv_lam;
     if (a.normalize) {
@@ -1139,7 +1144,7 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
             se += e;
         }
     }
-    se = block_sum4(se, red);
+    se = block_sum4(se, red + 12);
     const float inv_se = 1.0f / se;
     if (first) {
         if (a.w_out) {
