@@ -109,7 +109,11 @@ int launch_update(const d4_problem* p, const float* eps, const float* r, const f
         int grid = std::max(1, std::min(512, (D + 1) / 2));
         if (const int g = g_opt_update_grid.load()) grid = std::max(1, std::min(D, g));
         switch (J) {
-            case 1: hipLaunchKernelGGL(k_softmax_update_reg<1>, dim3(grid), dim3(256), 0, st, a); break;
+            case 1:
+                // up to 256 samples fit one wave's float4 columns
+                if (M <= 256) hipLaunchKernelGGL(k_softmax_update_wave, dim3(grid), dim3(64), 0, st, a);
+                else hipLaunchKernelGGL(k_softmax_update_reg<1>, dim3(grid), dim3(256), 0, st, a);
+                break;
             case 2: hipLaunchKernelGGL(k_softmax_update_reg<2>, dim3(grid), dim3(256), 0, st, a); break;
             case 4: hipLaunchKernelGGL(k_softmax_update_reg<4>, dim3(grid), dim3(256), 0, st, a); break;
             case 8: hipLaunchKernelGGL(k_softmax_update_reg<8>, dim3(grid), dim3(256), 0, st, a); break;

@@ -1066,9 +1066,14 @@ __device__ __forceinline__ void block_sum_max4(float& s, float& m, float* red) {
     m = fmaxf(fmaxf(red[4], red[5]), fmaxf(red[6], red[7]));
 }
 
-template <int J, int AUX = 0>
+// NW = 1 is the one-wave form for up to 256 samples (J = 1): its reductions
+// stay in the wave and take no barrier, and each adds the +0.0 that the
+// idle waves of the four-wave form contribute, so both forms give the same
+// bits.
+template <int J, int AUX = 0, int NW = 4>
 __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0, int e1, bool first) {
 #pragma clang fp contract(off)
+    static_assert(NW == 4 || (NW == 1 && J == 1), "the one-wave form owns one float4 column per lane");
     // statistics slots: sum and maximum [0, 8), squares [8, 12), exponentials [12, 16)
     __shared__ float red[16];
     constexpr int UPD_ROWS = upd_rows(J);
@@ -1109,7 +1114,12 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
             mx = fmaxf(fmaxf(mx, fmaxf(w[j].x, w[j].y)), fmaxf(w[j].z, w[j].w));
         }
     }
-    block_sum_max4(sum, mx, red);
+    if constexpr (NW == 4) {
+        block_sum_max4(sum, mx, red);
+    } else {
+        sum = wave_sum(sum) + 0.0f;
+        mx = fmaxf(wave_max(mx), -INFINITY);
+    }
     const float mean = sum / (float)M;
     float q = 0.0f;
 #pragma unroll
@@ -1125,7 +1135,7 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
             q = __builtin_fmaf(d, d, q);
         }
     }
-    q = block_sum4(q, red + 8);
+    q = NW == 4 ? block_sum4(q, red + 8) : wave_sum(q) + 0.0f;
     const bool bad = !isfinite(mean) || !isfinite(q) || !isfinite(mx);
     float mu = 0.0f, scale = a.inv_lam;
     if (a.normalize) {
@@ -1144,7 +1154,7 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
             se += e;
         }
     }
-    se = block_sum4(se, red + 12);
+    se = NW == 4 ? block_sum4(se, red + 12) : wave_sum(se) + 0.0f;
     const float inv_se = 1.0f / se;
     if (first) {
         if (a.w_out) {
@@ -1172,14 +1182,23 @@ __device__ __forceinline__ void softmax_update_block(const UpdateArgs& a, int e0
             }
             acc[rr] = wave_sum((c0 + c1) + (c2 + c3));
         }
-        __syncthreads();
-        if (lane == 0)
+        if constexpr (NW == 4) {
+            __syncthreads();
+            if (lane == 0)
 #pragma unroll
-            for (int rr = 0; rr < UPD_ROWS; ++rr) rowred[rr][wave] = acc[rr];
-        __syncthreads();
-        if (tid < UPD_ROWS && e + tid < e1) {
-            const float t = (rowred[tid][0] + rowred[tid][1]) + (rowred[tid][2] + rowred[tid][3]);
-            a.du_out[e + tid] = a.os * (a.du_in[e + tid] * a.ms + s_inv * t);
+                for (int rr = 0; rr < UPD_ROWS; ++rr) rowred[rr][wave] = acc[rr];
+            __syncthreads();
+            if (tid < UPD_ROWS && e + tid < e1) {
+                const float t = (rowred[tid][0] + rowred[tid][1]) + (rowred[tid][2] + rowred[tid][3]);
+                a.du_out[e + tid] = a.os * (a.du_in[e + tid] * a.ms + s_inv * t);
+            }
+        } else {
+            // every lane holds every row's sum; lane rr writes row e + rr
+            float t = 0.0f;
+#pragma unroll
+            for (int rr = 0; rr < UPD_ROWS; ++rr) t = tid == rr ? acc[rr] : t;
+            t = t + 0.0f;
+            if (tid < UPD_ROWS && e + tid < e1) a.du_out[e + tid] = a.os * (a.du_in[e + tid] * a.ms + s_inv * t);
         }
     }
 }
@@ -1190,6 +1209,13 @@ __global__ void __launch_bounds__(256) k_softmax_update_reg(const UpdateArgs a) 
     const int e0 = (int)((long long)a.D * blockIdx.x / gridDim.x);
     const int e1 = (int)((long long)a.D * (blockIdx.x + 1) / gridDim.x);
     softmax_update_block<J>(a, e0, e1, blockIdx.x == 0);
+}
+
+// The same with one wave per workgroup, for up to 256 samples.
+static __global__ void __launch_bounds__(64) k_softmax_update_wave(const UpdateArgs a) {
+    const int e0 = (int)((long long)a.D * blockIdx.x / gridDim.x);
+    const int e1 = (int)((long long)a.D * (blockIdx.x + 1) / gridDim.x);
+    softmax_update_block<1, 0, 1>(a, e0, e1, blockIdx.x == 0);
 }
 
 static __global__ void k_fill(float* p, int n, float v) {

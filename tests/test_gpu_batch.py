@@ -24,6 +24,9 @@ def _mix(count, M, N, seed=0, n_range=(2, 32), t_range=(9, 61)):
 
 
 def test_batch_equals_single_problem_runs(L):
+    # M = 160: the single-problem path updates with its one-wave form
+    # (k_softmax_update_wave), the batched form with four waves per
+    # workgroup; both must give the same plans bit for bit
     inst = _mix(7, 160, 12, seed=3)
     inst.append(W.holo3d_sphere(n=32, horizon=20, n_samples=160))
     inst[-1] = (inst[-1][0].replace(n_steps=12, instance_id=7), inst[-1][1], inst[-1][2])
