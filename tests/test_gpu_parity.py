@@ -180,6 +180,29 @@ def test_score_update_parity(L, name, p, x0, g, normalize):
     assert np.all(np.abs(_np(du_out) - ref) <= _update_tol(du_in, ms[step], sg[step], os_[step]))
 
 
+@pytest.mark.parametrize("M", [4, 128, 256, 260, 1024, 1028])
+def test_score_update_forms_at_their_boundaries(L, M):
+    """The update kernel's forms around their boundaries: the one-wave form
+    (M <= 256, a multiple of 4), the four-wave register form (J = 1 and 2)
+    and, at 1028, two float4 columns for some lanes and one for others;
+    each against the oracle's weighted update (Eqs. mc, mbd-denoising), with
+    every row of a range that is not a multiple of the rows per pass."""
+    print(f"case update forms M={M}", flush=True)
+    q, _, _ = W.holo2d_circle(n=3, horizon=9, n_samples=M)
+    rng = np.random.default_rng(M)
+    step = 7
+    eps = L.noise(q, 2, step)
+    r = (rng.normal(size=M) * 0.05 + 0.4).astype(np.float32)
+    du_in = (rng.normal(size=q.D) * 0.4).astype(np.float32)
+    du_out, w = L.score_update(q, _cu(r), eps, _cu(du_in), step)
+    ms, sg, os_ = osched.step_scalars(q.n_steps, q.beta_min, q.beta_max)
+    ref, wref = ombd.mc_update(du_in, _np(eps), r, ms[step], sg[step], os_[step], q.temperature, True)
+    wg = _np(w)
+    assert abs(wg.astype(np.float64).sum() - 1) < 1e-5
+    assert np.all(np.abs(wg - wref) <= 2e-5 * wref.max() + 1e-4 * wref)
+    assert np.all(np.abs(_np(du_out) - ref) <= _update_tol(du_in, ms[step], sg[step], os_[step]))
+
+
 def test_score_update_degenerate_rewards(L):
     p, x0, g = W.holo2d_circle(n=4, horizon=10, n_samples=200)
     eps = L.noise(p, 0, 5)
