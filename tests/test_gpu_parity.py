@@ -180,13 +180,15 @@ def test_score_update_parity(L, name, p, x0, g, normalize):
     assert np.all(np.abs(_np(du_out) - ref) <= _update_tol(du_in, ms[step], sg[step], os_[step]))
 
 
-@pytest.mark.parametrize("M", [4, 128, 256, 260, 1024, 1028])
+@pytest.mark.parametrize("M", [4, 128, 256, 260, 1024, 1028, 16384])
 def test_score_update_forms_at_their_boundaries(L, M):
     """The update kernel's forms around their boundaries: the one-wave form
     (M <= 256, a multiple of 4), the four-wave register form (J = 1 and 2)
     and, at 1028, two float4 columns for some lanes and one for others;
     each against the oracle's weighted update (Eqs. mc, mbd-denoising), with
-    every row of a range that is not a multiple of the rows per pass."""
+    every row of a range that is not a multiple of the rows per pass; 16384,
+    the largest sample count one workgroup's weights cover, takes sixteen
+    columns per lane."""
     print(f"case update forms M={M}", flush=True)
     q, _, _ = W.holo2d_circle(n=3, horizon=9, n_samples=M)
     rng = np.random.default_rng(M)
@@ -201,6 +203,15 @@ def test_score_update_forms_at_their_boundaries(L, M):
     assert abs(wg.astype(np.float64).sum() - 1) < 1e-5
     assert np.all(np.abs(wg - wref) <= 2e-5 * wref.max() + 1e-4 * wref)
     assert np.all(np.abs(_np(du_out) - ref) <= _update_tol(du_in, ms[step], sg[step], os_[step]))
+
+
+def test_score_update_refuses_more_samples_than_a_workgroup_weights(L):
+    """Above 16384 samples the update is refused (D4_EUNSUPPORTED) before any launch."""
+    q, _, _ = W.holo2d_circle(n=2, horizon=3, n_samples=16388)
+    eps = torch.zeros((q.D, q.n_samples), device="cuda")
+    with pytest.raises(L.D4Error) as e:
+        L.score_update(q, torch.zeros(q.n_samples, device="cuda"), eps, torch.zeros(q.D, device="cuda"), 1)
+    assert e.value.code == L.D4_EUNSUPPORTED
 
 
 def test_score_update_degenerate_rewards(L):
