@@ -36,7 +36,7 @@ enum {
     D4_ENOMEM = -2,        /* device allocation failed */
     D4_EHIP = -3,          /* a HIP runtime call failed */
     D4_ENONFINITE = -4,    /* a reward was NaN or infinite (stats.status) */
-    D4_EUNSUPPORTED = -5   /* shape beyond this build's limits */
+    D4_EUNSUPPORTED = -5   /* shape or form beyond the library's limits */
 };
 
 /* Robot models (Section V).  HOLO2D/HOLO3D: x = [p, v], u = a.  UNICYCLE:

@@ -339,7 +339,7 @@ int32_t d4_set_option(int32_t option, int32_t value) {
             if (value != 0 && value != 1) return fail(D4_EINVAL, "D4_OPT_BATCH_PERSISTENT takes 0 or 1, not %d", value);
             // the persistent step did not finish on the GPU and is switched off
             // until the cause is found (the two-launch form serves every batch)
-            if (value == 1) return fail(D4_EUNSUPPORTED, "the persistent batched step is switched off in this build");
+            if (value == 1) return fail(D4_EUNSUPPORTED, "the persistent batched step is switched off");
             g_opt_batch_persistent.store(value);
             return D4_OK;
         case D4_OPT_GEMM_TILE:
