@@ -179,3 +179,19 @@ def test_noalloc_entry_rejects_before_any_launch(L):
     assert lib.d4_denoise_iter_noalloc(ctypes.byref(cq), ptr, ptr, ptr, 70000, None, None, None) == L.D4_EINVAL
     bad = L.to_c(q.replace(n_robots=0))
     assert lib.d4_denoise_iter_noalloc(ctypes.byref(bad), ptr, ptr, ptr, 0, None, None, None) == L.D4_EINVAL
+
+
+def test_bench_measures_one_gpu_and_reports_its_source_hash():
+    """bench.py refuses a multi-GPU run with a message, before touching a
+    device, and --source-hash prints the hash that keys the stored traffic."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, cwd=ROOT, timeout=300)
+    assert res.returncode != 0 and "one GPU" in (res.stdout + res.stderr)
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--source-hash"], capture_output=True,
+                         text=True, cwd=ROOT, timeout=300)
+    assert res.returncode == 0
+    h = res.stdout.strip().splitlines()[-1]
+    assert re.fullmatch(r"[0-9a-f]{16}", h) and h == bench.kernel_source_hash()
