@@ -360,6 +360,8 @@ def main():
     ap.add_argument("--runs", type=int, default=30, help="runs per cell of the sensitivity sweep")
     ap.add_argument("--success-runs", type=int, default=50, help="runs per scenario of first_success")
     ap.add_argument("--scenarios", default="circle,random", help="scenarios of first_success")
+    ap.add_argument("--temperature", type=float, default=None,
+                    help="softmax temperature of first_success (default: the workload's 0.1)")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched experiment: time the batched form only (for profiling runs)")
     ap.add_argument("--no-tune", action="store_true",
@@ -418,7 +420,8 @@ def main():
                                 "frac": head["frac_of_peak"], "traffic": None},
                    "details": res}
         elif args.experiment == "first_success":
-            res = [E.first_success(L, scenario=sc, n=t, radius=args.radius or 4.0, runs=args.success_runs, log=log)
+            res = [E.first_success(L, scenario=sc, n=t, radius=args.radius or 4.0, runs=args.success_runs,
+                                   temperature=args.temperature, log=log)
                    for sc in args.scenarios.split(",") for t in (int(x) for x in args.teams.split(","))]
             head = [r for r in res if r["scenario"] == "circle" and r["robots"] == 16] or res
             out = {"metric": "mean wall time to the first conflict-free plan, 16 robots 2D holonomic, antipodal circle",
